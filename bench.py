@@ -1,0 +1,195 @@
+"""Benchmark: active-cell MLUPS of the progressive-mesh two-component LBM
+step on one GPU, with the HBM roofline of the dominant kernel and the CPU
+oracle timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 192]
+
+Workload: porous injection, 192^3 lattice in 16^3 blocks, random
+non-overlapping spheres of radius 4-12 at porosity 0.65, liquid injected at
+x = 0, only the inlet blocks meshed at t = 0, FP32.  A step is one call of
+the whole hot path: moments, pseudo-potential and criterion, activation,
+initialisation of new blocks, forces, collision and streaming.
+
+Prints one JSON line.  value = active cells updated per second (millions),
+summed over the K timed steps (cells of active blocks, solid or not).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of the collide/stream kernel per fluid cell of an active
+# block (two components, FP32): 2 x 19 populations read and written once
+# (304 B), the cell's two potentials read once (8 B), its mask word (4 B).
+K2_BYTES_PER_FLUID_CELL = 2 * 19 * 4 * 2 + 2 * 4 + 4
+# per solid cell of an active block the kernel reads only the mask word
+K2_BYTES_PER_SOLID_CELL = 4
+
+
+def active_cells_per_step(trace: np.ndarray, n0: int, t0: int, k: int) -> np.ndarray:
+    """Active blocks during each of steps t0 .. t0+k-1, from the activation
+    trace (a block recorded at step s takes part from step s on)."""
+    steps = trace[:, 0] if len(trace) else np.zeros(0, dtype=np.int64)
+    n = np.empty(k, dtype=np.int64)
+    for j in range(k):
+        n[j] = n0 + int(np.count_nonzero(steps <= t0 + j))
+    return n
+
+
+def fluid_cells_of_active(case, trace, t) -> int:
+    """Fluid cells in the blocks active during step t."""
+    p = case.params
+    B = p["block"]
+    nbx, nby, nbz = p["nx"] // B, p["ny"] // B, p["nz"] // B
+    fluid = (case.solid.reshape(nbz, B, nby, B, nbx, B) == 0).sum(axis=(1, 3, 5)).reshape(-1)
+    act = case.active_blocks.astype(bool).copy() if case.active_blocks is not None else fluid > 0
+    if len(trace):
+        act[trace[trace[:, 0] <= t, 1]] = True
+    return int(fluid[act].sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--size", type=int, default=192)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (the whole lattice lives on one MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1510_03560_amd import lbm
+    from paper_1510_03560_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n = args.size
+    t_gen = time.time()
+    case = W.porous_injection(n, args.seed, steps=args.warmup + args.steps)
+    print(f"bench: {case.name} porosity {case.info['porosity']:.4f} generated in {time.time() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    K, Wm = args.steps, args.warmup
+
+    def timed_run(progressive: bool):
+        sim = lbm.Simulation(case, progressive=progressive)
+        sim.step(Wm)
+        torch.cuda.synchronize()
+        st0 = sim.stats()
+        tr0 = sim.trace()
+        n_before = st0["n_active"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter()
+        e0.record()
+        sim.step(K)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_wall
+        ms = e0.elapsed_time(e1)
+        st = sim.stats()
+        tr = sim.trace()
+        new = tr[len(tr0):]
+        nact = active_cells_per_step(new, n_before, Wm, K) if progressive else np.full(K, st["n_active"])
+        out = dict(ms=ms, wall=wall, stats=st, active_blocks_per_step=nact, trace=tr)
+        return sim, out
+
+    sim_p, prog = timed_run(True)
+    print(f"bench: progressive {K} steps {prog['ms']:.1f} ms, blocks {prog['stats']['n_active']}"
+          f"/{prog['stats']['n_fluid_blocks']}, leak {prog['stats']['leak']}", file=sys.stderr, flush=True)
+    if prog["stats"]["numeric_error"]:
+        print("bench: numeric error in the progressive run", file=sys.stderr)
+    sim_p.close()
+    sim_s, stat = timed_run(False)
+    print(f"bench: static {K} steps {stat['ms']:.1f} ms", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel on the full mesh: per-kernel HIP events
+    lbm.lbm_timing_enable(sim_s.h, True)
+    kprof_steps = min(K, 200)
+    sim_s.step(kprof_steps)
+    times = lbm.lbm_timing_read(sim_s.h)
+    lbm.lbm_timing_enable(sim_s.h, False)
+    sim_s.close()
+    cnt, tot = times["collide_stream"]
+    k2_ms = tot / max(cnt, 1)
+    fluid_full = fluid_cells_of_active(case.static_twin(), np.zeros((0, 2), np.int32), 0)
+    cells_full = stat["stats"]["n_active"] * 4096
+    k2_bytes = fluid_full * K2_BYTES_PER_FLUID_CELL + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
+    achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
+
+    cells_p = int(prog["active_blocks_per_step"].sum()) * 4096
+    value = cells_p / (prog["ms"] * 1e-3) / 1e6
+    domain_cells = case.N * K
+    res = {
+        "metric": "active-cell MLUPS",
+        "value": round(value, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(prog["ms"] / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"porous injection {n}^3, 16^3 blocks, spheres r 4-12, porosity "
+                        f"{case.info['porosity']:.3f}, progressive mesh from the inlet blocks, FP32",
+            "lattice": [n, n, n], "block": 16, "components": 2, "seed": args.seed,
+            "active_blocks_start": int(prog["active_blocks_per_step"][0]),
+            "active_blocks_end": int(prog["active_blocks_per_step"][-1]),
+            "fluid_blocks": int(prog["stats"]["n_fluid_blocks"]),
+        },
+        "domain_mlups_eq16": round(domain_cells / (prog["ms"] * 1e-3) / 1e6, 2),
+        "static_ms_per_step": round(stat["ms"] / K, 4),
+        "progressive_over_static_time": round(prog["ms"] / stat["ms"], 4),
+        "static_active_cell_mlups": round(cells_full * K / (stat["ms"] * 1e-3) / 1e6, 2),
+        "leak": int(prog["stats"]["leak"]),
+        "kernel_ms_per_launch": {k: round(v[1] / max(v[0], 1), 5) for k, v in times.items()},
+        "roofline": {
+            "kernel": "collide_stream",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": int(k2_bytes),
+            "launch_ms": round(k2_ms, 5),
+        },
+    }
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        used = oracle.set_threads(threads)
+        ref = oracle.Sim(case.params, case.solid, None, None, None)
+        t = time.perf_counter()
+        ref.step(args.cpu_steps)
+        dt = time.perf_counter() - t
+        res["cpu_baseline"] = {
+            "value": round(cells_full * args.cpu_steps / dt / 1e6, 3),
+            "unit": "MLUPS",
+            "cores": used,
+            "kind": "oracle",
+            "sample": f"{args.cpu_steps} steps of the same {n}^3 lattice on the static mesh "
+                      f"({stat['stats']['n_active']} active blocks), FP64, OpenMP",
+        }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,670 @@
+// Host runtime and C ABI of the progressive-mesh lattice Boltzmann library
+// (declared in include/lbm.h).  Owns the device buffers of a handle, validates
+// arguments, derives the constants of the run and enqueues the kernels of
+// lbm_kernels.hip on the handle's stream.  The per-step loop never waits for
+// the GPU: block counts live in device memory and every grid is sized to the
+// pool capacity, with surplus workgroups exiting at once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kTraceCap = 1 << 20;
+const char* const kKernelNames[LBM_NUM_KERNELS] = {"moments_psi_criterion", "activate", "init_blocks",
+                                                   "collide_stream"};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_params user{};
+  Params P{};
+  Buffers D{};
+  hipStream_t stream = nullptr;
+  lbm_allocator alloc{};
+  bool custom_alloc = false;
+  bool geometry = false;
+  int64_t step = 0;
+  int rbuf = 0;
+  int n_fluid_blocks = 0;
+  int64_t fluid_cells = 0;
+  int64_t bytes = 0;
+  int64_t slot_bytes = 0;
+  std::vector<uint8_t> bfluid_h;
+  std::vector<uint8_t> binlet_h;  // block holds an inlet node
+  std::vector<void*> owned;
+  float* init_rho = nullptr;
+  float* init_u = nullptr;
+  int32_t* ids_dev = nullptr;
+  int ids_cap = 0;
+  double* mass_dev = nullptr;
+  float* scratch_f = nullptr;  // small device scratch (rest state)
+  int* scratch_i = nullptr;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs per launch
+  std::vector<int> ev_kernel;
+  int64_t t_count[LBM_NUM_KERNELS] = {0, 0, 0, 0};
+  double t_ms[LBM_NUM_KERNELS] = {0, 0, 0, 0};
+  std::string err;
+};
+
+namespace {
+
+int fail(lbm_t* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h)
+    h->err = buf;
+  else
+    g_create_error = buf;
+  return code;
+}
+
+#define HIP_TRY(h, call)                                                                      \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail((h), LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(lbm_t* h, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 4;
+  if (h->custom_alloc) {
+    p = h->alloc.alloc(bytes, h->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    h->owned.push_back(p);
+    h->bytes += (int64_t)bytes;
+  }
+  return p;
+}
+
+void dev_free_all(lbm_t* h) {
+  for (void* p : h->owned) {
+    if (h->custom_alloc)
+      h->alloc.free(p, h->alloc.ctx);
+    else
+      (void)hipFree(p);
+  }
+  h->owned.clear();
+}
+
+void dev_free_one(lbm_t* h, void* p, size_t bytes) {
+  for (size_t k = 0; k < h->owned.size(); ++k)
+    if (h->owned[k] == p) {
+      h->owned.erase(h->owned.begin() + (long)k);
+      break;
+    }
+  if (h->custom_alloc)
+    h->alloc.free(p, h->alloc.ctx);
+  else
+    (void)hipFree(p);
+  h->bytes -= (int64_t)bytes;
+}
+
+// Peng-Robinson constants (Eq 7): Tc = (0.07780 / 0.45724) a / (b R),
+// theta = [1 + kappa (1 - sqrt(T/Tc))]^2, kappa = 0.37464 + 1.54226 w - 0.26992 w^2.
+void eos_constants(const lbm_params& p, double& RT, double& a_theta) {
+  const double Tc = (0.07780 / 0.45724) * p.eos_a / (p.eos_b * p.eos_R);
+  const double T = p.T_over_Tc * Tc;
+  const double k = 0.37464 + 1.54226 * p.eos_omega - 0.26992 * p.eos_omega * p.eos_omega;
+  const double s = 1.0 + k * (1.0 - std::sqrt(T / Tc));
+  RT = p.eos_R * T;
+  a_theta = p.eos_a * s * s;
+}
+
+double psi_host(const lbm_params& p, int a, double rho) {
+  double RT, at;
+  eos_constants(p, RT, at);
+  const double g = p.g[a][a];
+  if (g == 0.0) return 0.0;
+  const double b = p.eos_b;
+  const double pr = rho * RT / (1.0 - b * rho) - at * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+  const double rad = 2.0 * (pr - rho / 3.0) / (g / 3.0);
+  return rad > 0.0 ? std::sqrt(rad) : 0.0;
+}
+
+const int kEx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+const int kEy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+const int kEz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+double w_host(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+int validate(const lbm_params* p) {
+  if (!p) return fail(nullptr, LBM_EINVAL, "params is NULL");
+  if (p->block != kB) return fail(nullptr, LBM_EINVAL, "block must be 16 (got %d)", p->block);
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->nx % kB || p->ny % kB || p->nz % kB)
+    return fail(nullptr, LBM_EINVAL, "nx, ny, nz must be positive multiples of 16 (got %d %d %d)", p->nx, p->ny,
+                p->nz);
+  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31)
+    return fail(nullptr, LBM_EINVAL, "lattice larger than 2^31 cells");
+  if (p->ncomp != 1 && p->ncomp != 2) return fail(nullptr, LBM_EINVAL, "ncomp must be 1 or 2 (got %d)", p->ncomp);
+  if (p->shell_width < 1 || p->shell_width > kB / 2)
+    return fail(nullptr, LBM_EINVAL, "shell_width must be in 1..8 (got %d)", p->shell_width);
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] < 0 || p->bc[f] > 3) return fail(nullptr, LBM_EINVAL, "bc[%d] invalid (%d)", f, p->bc[f]);
+  for (int d = 0; d < 3; ++d)
+    if ((p->bc[2 * d] == LBM_BC_PERIODIC) != (p->bc[2 * d + 1] == LBM_BC_PERIODIC))
+      return fail(nullptr, LBM_EINVAL, "faces %d and %d: periodic must be set on both or neither", 2 * d, 2 * d + 1);
+  if (p->store != LBM_STORE_F32)
+    return fail(nullptr, LBM_EINVAL, "store %d not supported by this build", p->store);
+  if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
+  if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
+  if (p->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved must be 0");
+  for (int a = 0; a < p->ncomp; ++a) {
+    if (!(p->tau[a] > 0.5)) return fail(nullptr, LBM_EINVAL, "tau[%d] must exceed 0.5 (got %g)", a, p->tau[a]);
+    if (!(p->bg_rho[a] > 0.0)) return fail(nullptr, LBM_EINVAL, "bg_rho[%d] must be positive", a);
+  }
+  if (!(p->eos_b > 0.0) || !(p->eos_R > 0.0) || !(p->eos_a > 0.0) || !(p->T_over_Tc > 0.0))
+    return fail(nullptr, LBM_EINVAL, "equation of state constants must be positive");
+  if (p->ncomp == 2 && p->g[0][1] != p->g[1][0]) return fail(nullptr, LBM_EINVAL, "g[0][1] must equal g[1][0]");
+  if (!(p->S >= 0.0)) return fail(nullptr, LBM_EINVAL, "S must be >= 0");
+  return LBM_OK;
+}
+
+int check_device_flags(lbm_t* h) {
+  int32_t ctrl[kNumCtrl];
+  HIP_TRY(h, hipMemcpy(ctrl, h->D.ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+  if (ctrl[kNumeric]) return fail(h, LBM_ENUMERIC, "a density became non-positive or non-finite");
+  if (ctrl[kPoolFull])
+    return fail(h, LBM_ENOMEM, "block pool full (%d slots); raise pool_blocks", h->P.capacity);
+  return LBM_OK;
+}
+
+int sync(lbm_t* h) {
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (h->step > 0 && h->init_rho) {
+    const int64_t N = (int64_t)h->P.nx * h->P.ny * h->P.nz;
+    dev_free_one(h, h->init_rho, sizeof(float) * h->P.ncomp * N);
+    h->init_rho = nullptr;
+    h->D.init_rho = nullptr;
+    if (h->init_u) {
+      dev_free_one(h, h->init_u, sizeof(float) * 3 * N);
+      h->init_u = nullptr;
+      h->D.init_u = nullptr;
+    }
+  }
+  return check_device_flags(h);
+}
+
+// Timed launch helper: records events around the launch when timing is on.
+template <typename Fn>
+int timed(lbm_t* h, int kernel, Fn&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (h->timing) {
+    HIP_TRY(h, hipEventCreate(&a));
+    HIP_TRY(h, hipEventCreate(&b));
+    HIP_TRY(h, hipEventRecord(a, h->stream));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "launch of %s: %s", kKernelNames[kernel], hipGetErrorString(e));
+  if (h->timing) {
+    HIP_TRY(h, hipEventRecord(b, h->stream));
+    h->ev.push_back(a);
+    h->ev.push_back(b);
+    h->ev_kernel.push_back(kernel);
+  }
+  return LBM_OK;
+}
+
+int collect_timing(lbm_t* h) {
+  for (size_t k = 0; k < h->ev_kernel.size(); ++k) {
+    float ms = 0.0f;
+    HIP_TRY(h, hipEventSynchronize(h->ev[2 * k + 1]));
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
+    h->t_ms[h->ev_kernel[k]] += ms;
+    h->t_count[h->ev_kernel[k]] += 1;
+    (void)hipEventDestroy(h->ev[2 * k]);
+    (void)hipEventDestroy(h->ev[2 * k + 1]);
+  }
+  h->ev.clear();
+  h->ev_kernel.clear();
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lbm_t** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, LBM_EINVAL, "allocator needs alloc and free");
+  lbm_t* h = new lbm_handle();
+  h->user = *p;
+  h->stream = (hipStream_t)stream;
+  if (alloc) {
+    h->alloc = *alloc;
+    h->custom_alloc = true;
+  }
+  Params& P = h->P;
+  P.nx = p->nx;
+  P.ny = p->ny;
+  P.nz = p->nz;
+  P.nbx = p->nx / kB;
+  P.nby = p->ny / kB;
+  P.nbz = p->nz / kB;
+  P.nb = P.nbx * P.nby * P.nbz;
+  P.ncomp = p->ncomp;
+  P.shell = p->shell_width;
+  for (int f = 0; f < 6; ++f) P.bc[f] = p->bc[f];
+  P.trace_cap = kTraceCap;
+  P.s_zero = p->S == 0.0 ? 1 : 0;
+  P.S = (float)p->S;
+  double RT, at;
+  eos_constants(*p, RT, at);
+  P.RT = (float)RT;
+  P.a_theta = (float)at;
+  P.b = (float)p->eos_b;
+  P.beta = (float)p->beta;
+  P.g_cross = p->ncomp == 2 ? (float)p->g[0][1] : 0.0f;
+  for (int a = 0; a < kMaxComp; ++a) {
+    const int aa = a < p->ncomp ? a : 0;
+    P.omega[a] = (float)(1.0 / p->tau[aa]);
+    P.g_self[a] = (float)p->g[aa][aa];
+    for (int d = 0; d < 3; ++d) P.body[a][d] = (float)p->body[aa][d];
+    P.psi_in[a] = (float)psi_host(*p, aa, p->inlet_rho[aa]);
+    // inlet populations: Eq 2 at (inlet_rho, inlet_u), FP64 then rounded
+    const double* u = p->inlet_u;
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < kQ; ++i) {
+      const double eu = kEx[i] * u[0] + kEy[i] * u[1] + kEz[i] * u[2];
+      P.f_in[a][i] = (float)(w_host(i) * p->inlet_rho[aa] * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    }
+  }
+  // rest state on the device with the kernels' own arithmetic
+  h->scratch_f = (float*)dev_alloc(h, sizeof(float) * 64);
+  h->scratch_i = (int*)dev_alloc(h, sizeof(int) * 4);
+  h->mass_dev = (double*)dev_alloc(h, sizeof(double) * 4);
+  h->D.ctrl = (int32_t*)dev_alloc(h, sizeof(int32_t) * kNumCtrl);
+  h->D.counters = (unsigned long long*)dev_alloc(h, sizeof(unsigned long long) * 4);
+  if (!h->scratch_f || !h->scratch_i || !h->mass_dev || !h->D.ctrl || !h->D.counters) {
+    dev_free_all(h);
+    delete h;
+    return fail(nullptr, LBM_ENOMEM, "device allocation failed");
+  }
+  float bg[2] = {(float)p->bg_rho[0], (float)(p->ncomp == 2 ? p->bg_rho[1] : p->bg_rho[0])};
+  float res[64];
+  int iters = 0;
+  hipError_t e = hipMemcpyAsync(h->scratch_f + 56, bg, sizeof bg, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_rest_state(P, h->scratch_f + 56, h->scratch_f, h->scratch_i, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, h->scratch_f, sizeof(float) * 48, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&iters, h->scratch_i, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->D.ctrl, 0, sizeof(int32_t) * kNumCtrl, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->D.counters, 0, sizeof(unsigned long long) * 4, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    std::string msg = hipGetErrorString(e);
+    dev_free_all(h);
+    delete h;
+    return fail(nullptr, LBM_EHIP, "rest state: %s", msg.c_str());
+  }
+  if (iters >= 100000) {
+    dev_free_all(h);
+    delete h;
+    return fail(nullptr, LBM_EINVAL, "the rest state did not converge (body force?)");
+  }
+  for (int a = 0; a < kMaxComp; ++a) {
+    const int aa = a < p->ncomp ? a : 0;
+    for (int i = 0; i < kQ; ++i) P.f_rest[a][i] = res[aa * kQ + i];
+    P.rho_rest[a] = res[kMaxComp * kQ + aa];
+    P.psi_rest[a] = res[kMaxComp * kQ + kMaxComp + aa];
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const double* u0) {
+  if (!h) return LBM_EINVAL;
+  if (h->geometry) return fail(h, LBM_ESTATE, "lbm_set_geometry called twice");
+  Params& P = h->P;
+  Buffers& D = h->D;
+  const int64_t N = (int64_t)P.nx * P.ny * P.nz;
+  // block classification on the host
+  h->bfluid_h.assign(P.nb, 0);
+  h->binlet_h.assign(P.nb, 0);
+  h->fluid_cells = 0;
+  for (int z = 0; z < P.nz; ++z)
+    for (int y = 0; y < P.ny; ++y)
+      for (int x = 0; x < P.nx; ++x) {
+        const int64_t n = x + (int64_t)P.nx * (y + (int64_t)P.ny * z);
+        if (solid && solid[n]) continue;
+        const int b = x / kB + P.nbx * (y / kB + P.nby * (z / kB));
+        h->bfluid_h[b] = 1;
+        h->fluid_cells++;
+        const bool on[6] = {x == 0, x == P.nx - 1, y == 0, y == P.ny - 1, z == 0, z == P.nz - 1};
+        for (int f = 0; f < 6; ++f)
+          if (on[f] && P.bc[f] == kInletFace) h->binlet_h[b] = 1;
+      }
+  h->n_fluid_blocks = 0;
+  for (int b = 0; b < P.nb; ++b) h->n_fluid_blocks += h->bfluid_h[b];
+  int cap = h->user.pool_blocks > 0 ? h->user.pool_blocks : h->n_fluid_blocks;
+  if (cap > P.nb) cap = P.nb;
+  if (cap < 1) cap = 1;
+  P.capacity = cap;
+  const int64_t slot_elems = (int64_t)P.ncomp * kQ * kCells;
+  const int64_t slots = cap + 1;
+  D.f[0] = (float*)dev_alloc(h, sizeof(float) * slot_elems * slots);
+  D.f[1] = (float*)dev_alloc(h, sizeof(float) * slot_elems * slots);
+  D.psi = (float*)dev_alloc(h, sizeof(float) * P.ncomp * kCells * slots);
+  D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * kCells * slots);
+  D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * kCells * cap) : nullptr;
+  D.block_slot = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
+  D.slot_block = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
+  D.bfluid = (uint8_t*)dev_alloc(h, P.nb);
+  D.solid = (uint8_t*)dev_alloc(h, (size_t)N);
+  D.request = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
+  D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
+  if (!D.f[0] || !D.f[1] || !D.psi || !D.mask || (h->user.progressive && !D.uprev) || !D.block_slot ||
+      !D.slot_block || !D.bfluid || !D.solid || !D.request || !D.trace)
+    return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
+  h->slot_bytes = (int64_t)(2 * slot_elems + P.ncomp * kCells + kCells) * 4 +
+                  (h->user.progressive ? (int64_t)P.ncomp * 3 * kCells * 4 : 0);
+  // initial fields, FP32; NaN marks a component of a cell at the rest state
+  if (rho0 || u0) {
+    std::vector<float> r((size_t)P.ncomp * N), u(u0 ? (size_t)3 * N : 0);
+    const float nan = std::nanf("");
+    for (int a = 0; a < P.ncomp; ++a)
+      for (int64_t n = 0; n < N; ++n) {
+        const double rv = rho0 ? rho0[a * N + n] : h->user.bg_rho[a];
+        const bool zero_u = !u0 || (u0[n] == 0.0 && u0[N + n] == 0.0 && u0[2 * N + n] == 0.0);
+        r[a * N + n] = (rv == h->user.bg_rho[a] && zero_u) ? nan : (float)rv;
+      }
+    if (u0)
+      for (int64_t k = 0; k < 3 * N; ++k) u[k] = (float)u0[k];
+    h->init_rho = (float*)dev_alloc(h, sizeof(float) * r.size());
+    if (!h->init_rho) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
+    HIP_TRY(h, hipMemcpy(h->init_rho, r.data(), sizeof(float) * r.size(), hipMemcpyHostToDevice));
+    D.init_rho = h->init_rho;
+    if (u0) {
+      h->init_u = (float*)dev_alloc(h, sizeof(float) * u.size());
+      if (!h->init_u) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
+      HIP_TRY(h, hipMemcpy(h->init_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice));
+      D.init_u = h->init_u;
+    }
+  }
+  std::vector<uint8_t> sol((size_t)N, 0);
+  if (solid)
+    for (int64_t n = 0; n < N; ++n) sol[n] = solid[n] ? 1 : 0;
+  HIP_TRY(h, hipMemcpy(D.solid, sol.data(), (size_t)N, hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(D.bfluid, h->bfluid_h.data(), P.nb, hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemsetAsync(D.request, 0, sizeof(int32_t) * P.nb, h->stream));
+  // the rest slot, in both population buffers
+  for (int b = 0; b < 2; ++b) {
+    hipError_t e = launch_init_slots(P, D, b, P.capacity, 1, false, false, h->stream);
+    if (e != hipSuccess) return fail(h, LBM_EHIP, "init rest slot: %s", hipGetErrorString(e));
+  }
+  std::vector<int32_t> bslot(P.nb, -1), sblock;
+  if (!h->user.progressive) {
+    for (int b = 0; b < P.nb; ++b)
+      if (h->bfluid_h[b]) {
+        bslot[b] = (int32_t)sblock.size();
+        sblock.push_back(b);
+      }
+    if ((int)sblock.size() > cap) return fail(h, LBM_ENOMEM, "pool_blocks smaller than the blocks holding fluid");
+  }
+  HIP_TRY(h, hipMemcpy(D.block_slot, bslot.data(), sizeof(int32_t) * P.nb, hipMemcpyHostToDevice));
+  if (!sblock.empty())
+    HIP_TRY(h, hipMemcpy(D.slot_block, sblock.data(), sizeof(int32_t) * sblock.size(), hipMemcpyHostToDevice));
+  int32_t ctrl[kNumCtrl] = {0};
+  ctrl[kNActive] = (int32_t)sblock.size();
+  HIP_TRY(h, hipMemcpy(D.ctrl, ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+  if (!sblock.empty()) {
+    hipError_t e = launch_init_slots(P, D, 0, 0, (int)sblock.size(), false, true, h->stream);
+    if (e != hipSuccess) return fail(h, LBM_EHIP, "init blocks: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->geometry = true;
+  return LBM_OK;
+}
+
+int lbm_activate(lbm_t* h, const int32_t* ids, int32_t n) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_activate before lbm_set_geometry");
+  if (n < 0 || (n > 0 && !ids)) return fail(h, LBM_EINVAL, "bad block list");
+  if (n == 0) return LBM_OK;
+  for (int k = 0; k < n; ++k)
+    if (ids[k] < 0 || ids[k] >= h->P.nb) return fail(h, LBM_EINVAL, "block id %d out of range", ids[k]);
+  // mark requests on the host side of a small upload, then compact on the GPU
+  std::vector<int32_t> req(h->P.nb, 0);
+  HIP_TRY(h, hipMemcpyAsync(req.data(), h->D.request, sizeof(int32_t) * h->P.nb, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (int k = 0; k < n; ++k) req[ids[k]] = 1;
+  HIP_TRY(h, hipMemcpy(h->D.request, req.data(), sizeof(int32_t) * h->P.nb, hipMemcpyHostToDevice));
+  hipError_t e = launch_activate(h->P, h->D, (int)h->step, h->stream);
+  if (e == hipSuccess) e = launch_init_slots(h->P, h->D, h->rbuf, 0, 0, true, h->step == 0, h->stream);
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "activation: %s", hipGetErrorString(e));
+  return sync(h);
+}
+
+int lbm_step(lbm_t* h, int32_t nsteps) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_step before lbm_set_geometry");
+  if (nsteps < 0) return fail(h, LBM_EINVAL, "nsteps < 0");
+  const Params& P = h->P;
+  if (h->step == 0 && nsteps > 0 && h->user.progressive) {
+    std::vector<int32_t> bslot(P.nb);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(bslot.data(), h->D.block_slot, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost));
+    for (int b = 0; b < P.nb; ++b)
+      if (h->binlet_h[b] && bslot[b] < 0)
+        return fail(h, LBM_EINVAL, "block %d holds inlet nodes but is not active at t = 0", b);
+  }
+  for (int32_t k = 0; k < nsteps; ++k) {
+    const bool pull = h->step > 0;
+    const int rb = h->rbuf;
+    int rc;
+    if (h->user.progressive) {
+      const int mode = h->step == 0 ? 1 : 2;
+      rc = timed(h, 0, [&] { return launch_moments(P, h->D, rb, pull, mode, h->stream); });
+      if (rc) return rc;
+      rc = timed(h, 1, [&] { return launch_activate(P, h->D, (int)h->step, h->stream); });
+      if (rc) return rc;
+      rc = timed(h, 2, [&] { return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream); });
+      if (rc) return rc;
+    } else {
+      rc = timed(h, 0, [&] { return launch_moments(P, h->D, rb, pull, 0, h->stream); });
+      if (rc) return rc;
+    }
+    rc = timed(h, 3, [&] { return launch_collide(P, h->D, rb, pull, h->stream); });
+    if (rc) return rc;
+    h->rbuf ^= 1;
+    h->step++;
+  }
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_t* h) {
+  if (!h) return LBM_EINVAL;
+  return sync(h);
+}
+
+int lbm_moments_device(lbm_t* h, float* rho, float* u, float* umix) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_moments before lbm_set_geometry");
+  hipError_t e = launch_export(h->P, h->D, h->rbuf, h->step > 0, rho, u, umix, h->stream);
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "export: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_moments before lbm_set_geometry");
+  int rc = sync(h);
+  if (rc) return rc;
+  const Params& P = h->P;
+  const int64_t N = (int64_t)P.nx * P.ny * P.nz;
+  const size_t nr = (size_t)P.ncomp * N, nu = (size_t)P.ncomp * 3 * N, nm = (size_t)3 * N;
+  float* d_r = rho ? (float*)dev_alloc(h, sizeof(float) * nr) : nullptr;
+  float* d_u = u ? (float*)dev_alloc(h, sizeof(float) * nu) : nullptr;
+  float* d_m = umix ? (float*)dev_alloc(h, sizeof(float) * nm) : nullptr;
+  if ((rho && !d_r) || (u && !d_u) || (umix && !d_m)) {
+    if (d_r) dev_free_one(h, d_r, sizeof(float) * nr);
+    if (d_u) dev_free_one(h, d_u, sizeof(float) * nu);
+    if (d_m) dev_free_one(h, d_m, sizeof(float) * nm);
+    return fail(h, LBM_ENOMEM, "device allocation failed (moments)");
+  }
+  rc = lbm_moments_device(h, d_r, d_u, d_m);
+  std::vector<float> tmp;
+  auto fetch = [&](float* d, double* out, size_t n) -> int {
+    if (!d) return LBM_OK;
+    tmp.resize(n);
+    HIP_TRY(h, hipMemcpyAsync(tmp.data(), d, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (size_t k = 0; k < n; ++k) out[k] = (double)tmp[k];
+    return LBM_OK;
+  };
+  if (!rc) rc = fetch(d_r, rho, nr);
+  if (!rc) rc = fetch(d_u, u, nu);
+  if (!rc) rc = fetch(d_m, umix, nm);
+  if (d_r) dev_free_one(h, d_r, sizeof(float) * nr);
+  if (d_u) dev_free_one(h, d_u, sizeof(float) * nu);
+  if (d_m) dev_free_one(h, d_m, sizeof(float) * nm);
+  if (rc) return rc;
+  if (active) {
+    std::vector<int32_t> bslot(P.nb);
+    HIP_TRY(h, hipMemcpy(bslot.data(), h->D.block_slot, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost));
+    for (int z = 0; z < P.nz; ++z)
+      for (int y = 0; y < P.ny; ++y)
+        for (int x = 0; x < P.nx; ++x)
+          active[x + (int64_t)P.nx * (y + (int64_t)P.ny * z)] =
+              bslot[x / kB + P.nbx * (y / kB + P.nby * (z / kB))] >= 0 ? 1 : 0;
+  }
+  return check_device_flags(h);
+}
+
+int lbm_stats(lbm_t* h, lbm_stats_t* out) {
+  if (!h || !out) return LBM_EINVAL;
+  std::memset(out, 0, sizeof *out);
+  int rc = LBM_OK;
+  if (h->geometry) {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  int32_t ctrl[kNumCtrl] = {0};
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  HIP_TRY(h, hipMemcpy(ctrl, h->D.ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(cnt, h->D.counters, sizeof cnt, hipMemcpyDeviceToHost));
+  out->steps = h->step;
+  out->n_active = ctrl[kNActive];
+  out->n_fluid_blocks = h->n_fluid_blocks;
+  out->capacity = h->P.capacity;
+  out->store = h->user.store;
+  out->bytes_reserved = h->bytes;
+  out->bytes_active = h->slot_bytes * ctrl[kNActive];
+  out->leak = (int64_t)cnt[0];
+  out->clamps = (int64_t)cnt[1];
+  out->numeric_error = ctrl[kNumeric];
+  out->pool_full = ctrl[kPoolFull];
+  out->activations = ctrl[kTraceLen];
+  if (h->geometry) {
+    double m[4] = {0, 0, 0, 0};
+    HIP_TRY(h, hipMemsetAsync(h->mass_dev, 0, sizeof m, h->stream));
+    hipError_t e = launch_mass(h->P, h->D, h->rbuf, h->step > 0, h->mass_dev, h->stream);
+    if (e != hipSuccess) return fail(h, LBM_EHIP, "mass: %s", hipGetErrorString(e));
+    HIP_TRY(h, hipMemcpyAsync(m, h->mass_dev, sizeof m, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const double inactive_cells = (double)h->fluid_cells - m[2];
+    for (int a = 0; a < h->P.ncomp; ++a) out->mass[a] = m[a] + inactive_cells * (double)h->P.rho_rest[a];
+  }
+  return rc;
+}
+
+int lbm_trace(lbm_t* h, int32_t* out, int32_t cap) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return 0;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  int32_t ctrl[kNumCtrl];
+  HIP_TRY(h, hipMemcpy(ctrl, h->D.ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+  int32_t n = ctrl[kTraceLen];
+  int32_t avail = n < h->P.trace_cap ? n : h->P.trace_cap;
+  int32_t k = avail < cap ? avail : cap;
+  if (k > 0 && out) HIP_TRY(h, hipMemcpy(out, h->D.trace, sizeof(int32_t) * 2 * k, hipMemcpyDeviceToHost));
+  return n;
+}
+
+int lbm_debug_fields(lbm_t* h, int which, double* out) {
+  if (!h || !out) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_debug_fields before lbm_set_geometry");
+  if (which != LBM_DEBUG_PSI && which != LBM_DEBUG_FORCE) return fail(h, LBM_EINVAL, "which must be 0 or 1");
+  int rc = sync(h);
+  if (rc) return rc;
+  const Params& P = h->P;
+  const int64_t N = (int64_t)P.nx * P.ny * P.nz;
+  const size_t np = (size_t)P.ncomp * N, nf = (size_t)P.ncomp * 3 * N;
+  float* d_p = (float*)dev_alloc(h, sizeof(float) * np);
+  float* d_f = (float*)dev_alloc(h, sizeof(float) * nf);
+  if (!d_p || !d_f) {
+    if (d_p) dev_free_one(h, d_p, sizeof(float) * np);
+    if (d_f) dev_free_one(h, d_f, sizeof(float) * nf);
+    return fail(h, LBM_ENOMEM, "device allocation failed (debug)");
+  }
+  hipError_t e = hipMemsetAsync(d_p, 0, sizeof(float) * np, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d_f, 0, sizeof(float) * nf, h->stream);
+  // psi needs the moments pass of the current state first
+  if (e == hipSuccess) e = launch_moments(P, h->D, h->rbuf, h->step > 0, 0, h->stream);
+  if (e == hipSuccess) e = launch_debug_fields(P, h->D, h->rbuf, h->step > 0, d_p, d_f, h->stream);
+  std::vector<float> tmp(which == LBM_DEBUG_PSI ? np : nf);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tmp.data(), which == LBM_DEBUG_PSI ? d_p : d_f, sizeof(float) * tmp.size(),
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  dev_free_one(h, d_p, sizeof(float) * np);
+  dev_free_one(h, d_f, sizeof(float) * nf);
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "debug fields: %s", hipGetErrorString(e));
+  for (size_t k = 0; k < tmp.size(); ++k) out[k] = (double)tmp[k];
+  return LBM_OK;
+}
+
+int lbm_timing_enable(lbm_t* h, int enable) {
+  if (!h) return LBM_EINVAL;
+  h->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n) {
+  if (!h) return LBM_EINVAL;
+  int rc = collect_timing(h);
+  if (rc) return rc;
+  for (int k = 0; k < n && k < LBM_NUM_KERNELS; ++k) {
+    if (counts) counts[k] = h->t_count[k];
+    if (total_ms) total_ms[k] = h->t_ms[k];
+    h->t_count[k] = 0;
+    h->t_ms[k] = 0.0;
+  }
+  return LBM_OK;
+}
+
+const char* lbm_kernel_name(int32_t k) { return (k >= 0 && k < LBM_NUM_KERNELS) ? kKernelNames[k] : ""; }
+
+int lbm_destroy(lbm_t* h) {
+  if (!h) return LBM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  dev_free_all(h);
+  delete h;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_t* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal interface between the host runtime (lbm_api.cpp) and the HIP
+// kernels (lbm_kernels.hip) of the progressive-mesh lattice Boltzmann library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kQ = 19;          // D3Q19 directions
+constexpr int kB = 16;          // block edge
+constexpr int kCells = kB * kB * kB;
+constexpr int kMaxComp = 2;
+
+// Cell kinds, stored in bits 24..25 of the per-cell mask word.
+enum CellKind : uint32_t { kFluid = 0, kSolid = 1, kInlet = 2, kOutlet = 3 };
+constexpr int kKindShift = 24;
+
+// Face kinds (same values as LBM_BC_*).
+enum FaceKind : int { kPeriodic = 0, kWall = 1, kInletFace = 2, kOutletFace = 3 };
+
+// Control words in device memory.
+enum Ctrl : int {
+  kNActive = 0,     // active blocks (== slots in use)
+  kNewFirst = 1,    // first slot activated by the last activation pass
+  kNewCount = 2,    // number of slots activated by the last activation pass
+  kPoolFull = 3,    // set when a request did not fit the pool
+  kNumeric = 4,     // set when a density was non-positive or non-finite
+  kTraceLen = 5,    // activation trace entries written
+  kNumCtrl = 8
+};
+
+// Constants of one run, passed by value to every kernel.
+struct Params {
+  int nx, ny, nz;
+  int nbx, nby, nbz, nb;
+  int ncomp;
+  int shell;
+  int bc[6];
+  int capacity;      // usable slots; slot index `capacity` is the rest slot
+  int trace_cap;
+  int s_zero;        // criterion threshold is exactly zero
+  float S;
+  float omega[kMaxComp];   // 1/tau
+  float RT, a_theta, b;    // Peng-Robinson constants
+  float g_self[kMaxComp];
+  float g_cross;
+  float beta;
+  float body[kMaxComp][3];
+  float psi_in[kMaxComp];
+  float psi_rest[kMaxComp];
+  float rho_rest[kMaxComp];
+  float f_in[kMaxComp][kQ];    // populations imposed by inlet nodes
+  float f_rest[kMaxComp][kQ];  // rest populations (bitwise fixed point)
+};
+
+// Device buffers of one handle.
+struct Buffers {
+  float* f[2];            // populations, [(capacity+1)][ncomp][19][4096]
+  float* psi;             // [(capacity+1)][ncomp][4096]
+  uint32_t* mask;         // [(capacity+1)][4096]: bit i = link i bounces; kind in bits 24..25
+  float* uprev;           // [capacity][ncomp][3][4096] velocity of the previous step (criterion)
+  int32_t* block_slot;    // [nb] slot of a block, -1 when inactive
+  int32_t* slot_block;    // [capacity] block of a slot (the active list)
+  uint8_t* bfluid;        // [nb] block holds a non-solid cell
+  uint8_t* solid;         // [nx*ny*nz] solid flags of the whole lattice
+  int32_t* request;       // [nb] activation requests
+  int32_t* ctrl;          // [kNumCtrl]
+  unsigned long long* counters;  // [0] leak, [1] clamps
+  int32_t* trace;         // [trace_cap][2] (step, block)
+  const float* init_rho;  // [ncomp][N] initial densities, or null (used before the first step)
+  const float* init_u;    // [3][N] initial velocity, or null
+};
+
+// Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the
+// launch status.
+// Rest state: bg = device [2] background densities; out = device
+// [2*19 populations, 2 densities, 2 potentials]; iters = device int.
+hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream);
+hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first_slot_host, int count_host,
+                             bool from_device_counts, bool use_initial_fields, hipStream_t stream);
+hipError_t launch_moments(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
+                          hipStream_t stream);
+hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream);
+hipError_t launch_collide(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
+hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
+                         float* umix, hipStream_t stream);
+hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,
+                       hipStream_t stream);
+hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi,
+                               float* force, hipStream_t stream);
+
+}  // namespace lbm
