@@ -21,8 +21,8 @@ using namespace lbm;
 namespace {
 
 constexpr int kTraceCap = 1 << 20;
-const char* const kKernelNames[LBM_NUM_KERNELS] = {"moments_psi_criterion", "activate", "init_blocks",
-                                                   "collide_stream"};
+const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step",
+                                                   "fused_step_frontier"};
 
 std::string g_create_error;
 
@@ -55,8 +55,8 @@ struct lbm_handle {
   bool timing = false;
   std::vector<hipEvent_t> ev;   // pairs per launch
   std::vector<int> ev_kernel;
-  int64_t t_count[LBM_NUM_KERNELS] = {0, 0, 0, 0};
-  double t_ms[LBM_NUM_KERNELS] = {0, 0, 0, 0};
+  int64_t t_count[LBM_NUM_KERNELS] = {};
+  double t_ms[LBM_NUM_KERNELS] = {};
   std::string err;
 };
 
@@ -163,8 +163,8 @@ int validate(const lbm_params* p) {
   for (int d = 0; d < 3; ++d)
     if ((p->bc[2 * d] == LBM_BC_PERIODIC) != (p->bc[2 * d + 1] == LBM_BC_PERIODIC))
       return fail(nullptr, LBM_EINVAL, "faces %d and %d: periodic must be set on both or neither", 2 * d, 2 * d + 1);
-  if (p->store != LBM_STORE_F32)
-    return fail(nullptr, LBM_EINVAL, "store %d not supported by this build", p->store);
+  if (p->store != LBM_STORE_F32 && p->store != LBM_STORE_F16DEV)
+    return fail(nullptr, LBM_EINVAL, "store must be LBM_STORE_F32 or LBM_STORE_F16DEV (got %d)", p->store);
   if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
   if (p->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved must be 0");
@@ -269,6 +269,7 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   P.shell = p->shell_width;
   for (int f = 0; f < 6; ++f) P.bc[f] = p->bc[f];
   P.trace_cap = kTraceCap;
+  P.store = p->store;
   P.s_zero = p->S == 0.0 ? 1 : 0;
   P.S = (float)p->S;
   double RT, at;
@@ -293,7 +294,7 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
     }
   }
   // rest state on the device with the kernels' own arithmetic
-  h->scratch_f = (float*)dev_alloc(h, sizeof(float) * 64);
+  h->scratch_f = (float*)dev_alloc(h, sizeof(float) * 128);
   h->scratch_i = (int*)dev_alloc(h, sizeof(int) * 4);
   h->mass_dev = (double*)dev_alloc(h, sizeof(double) * 4);
   h->D.ctrl = (int32_t*)dev_alloc(h, sizeof(int32_t) * kNumCtrl);
@@ -304,11 +305,11 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
     return fail(nullptr, LBM_ENOMEM, "device allocation failed");
   }
   float bg[2] = {(float)p->bg_rho[0], (float)(p->ncomp == 2 ? p->bg_rho[1] : p->bg_rho[0])};
-  float res[64];
+  float res[128];
   int iters = 0;
-  hipError_t e = hipMemcpyAsync(h->scratch_f + 56, bg, sizeof bg, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = launch_rest_state(P, h->scratch_f + 56, h->scratch_f, h->scratch_i, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(res, h->scratch_f, sizeof(float) * 48, hipMemcpyDeviceToHost, h->stream);
+  hipError_t e = hipMemcpyAsync(h->scratch_f + 120, bg, sizeof bg, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_rest_state(P, h->scratch_f + 120, h->scratch_f, h->scratch_i, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(res, h->scratch_f, sizeof(float) * 96, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&iters, h->scratch_i, sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->D.ctrl, 0, sizeof(int32_t) * kNumCtrl, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->D.counters, 0, sizeof(unsigned long long) * 4, h->stream);
@@ -326,9 +327,15 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   }
   for (int a = 0; a < kMaxComp; ++a) {
     const int aa = a < p->ncomp ? a : 0;
-    for (int i = 0; i < kQ; ++i) P.f_rest[a][i] = res[aa * kQ + i];
-    P.rho_rest[a] = res[kMaxComp * kQ + aa];
-    P.psi_rest[a] = res[kMaxComp * kQ + kMaxComp + aa];
+    for (int i = 0; i < kQ; ++i) {
+      uint32_t bits;
+      std::memcpy(&bits, &res[aa * kQ + i], 4);
+      P.f_rest_bits[a][i] = bits;
+      P.f_rest[a][i] = res[2 * kQ + aa * kQ + i];
+    }
+    P.rho_ref_rest[a] = res[4 * kQ + aa];
+    P.rho_rest[a] = res[4 * kQ + 2 + aa];
+    P.psi_rest[a] = res[4 * kQ + 4 + aa];
   }
   *out = h;
   return LBM_OK;
@@ -362,24 +369,29 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   if (cap > P.nb) cap = P.nb;
   if (cap < 1) cap = 1;
   P.capacity = cap;
-  const int64_t slot_elems = (int64_t)P.ncomp * kQ * kCells;
-  const int64_t slots = cap + 1;
-  D.f[0] = (float*)dev_alloc(h, sizeof(float) * slot_elems * slots);
-  D.f[1] = (float*)dev_alloc(h, sizeof(float) * slot_elems * slots);
-  D.psi = (float*)dev_alloc(h, sizeof(float) * P.ncomp * kCells * slots);
-  D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * kCells * slots);
-  D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * kCells * cap) : nullptr;
+  const int64_t plane = (int64_t)(cap + 1) * kCells;
+  P.plane = (uint32_t)plane;
+  const size_t fsz = h->user.store == LBM_STORE_F16DEV ? 2 : 4;
+  const bool f16 = h->user.store == LBM_STORE_F16DEV;
+  D.f[0] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
+  D.f[1] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
+  D.rho[0] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
+  D.rho[1] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
+  D.psi = (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane);
+  D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * plane);
+  D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * plane) : nullptr;
   D.block_slot = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.slot_block = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
   D.bfluid = (uint8_t*)dev_alloc(h, P.nb);
   D.solid = (uint8_t*)dev_alloc(h, (size_t)N);
   D.request = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
-  if (!D.f[0] || !D.f[1] || !D.psi || !D.mask || (h->user.progressive && !D.uprev) || !D.block_slot ||
+  if (!D.f[0] || !D.f[1] || (f16 && (!D.rho[0] || !D.rho[1])) || !D.psi || !D.mask ||
+      (h->user.progressive && !D.uprev) || !D.block_slot ||
       !D.slot_block || !D.bfluid || !D.solid || !D.request || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
-  h->slot_bytes = (int64_t)(2 * slot_elems + P.ncomp * kCells + kCells) * 4 +
-                  (h->user.progressive ? (int64_t)P.ncomp * 3 * kCells * 4 : 0);
+  h->slot_bytes = (int64_t)kCells * ((int64_t)2 * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) + 4 * P.ncomp + 4 +
+                                     (h->user.progressive ? 12 * P.ncomp : 0));
   // initial fields, FP32; NaN marks a component of a cell at the rest state
   if (rho0 || u0) {
     std::vector<float> r((size_t)P.ncomp * N), u(u0 ? (size_t)3 * N : 0);
@@ -475,19 +487,21 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     const int rb = h->rbuf;
     int rc;
     if (h->user.progressive) {
+      // criterion on the frontier, then the requested blocks join this step
       const int mode = h->step == 0 ? 1 : 2;
-      rc = timed(h, 0, [&] { return launch_moments(P, h->D, rb, pull, mode, h->stream); });
+      rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, pull, mode, h->stream); });
       if (rc) return rc;
       rc = timed(h, 1, [&] { return launch_activate(P, h->D, (int)h->step, h->stream); });
       if (rc) return rc;
       rc = timed(h, 2, [&] { return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream); });
       if (rc) return rc;
-    } else {
-      rc = timed(h, 0, [&] { return launch_moments(P, h->D, rb, pull, 0, h->stream); });
+    }
+    rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, false, h->stream); });
+    if (rc) return rc;
+    if (h->user.progressive) {
+      rc = timed(h, 4, [&] { return launch_fused(P, h->D, rb, pull, true, h->stream); });
       if (rc) return rc;
     }
-    rc = timed(h, 3, [&] { return launch_collide(P, h->D, rb, pull, h->stream); });
-    if (rc) return rc;
     h->rbuf ^= 1;
     h->step++;
   }

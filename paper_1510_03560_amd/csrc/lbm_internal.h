@@ -38,6 +38,8 @@ struct Params {
   int shell;
   int bc[6];
   int capacity;      // usable slots; slot index `capacity` is the rest slot
+  uint32_t plane;    // elements per population plane: (capacity + 1) * 4096
+  int store;         // 0: FP32 populations, 1: FP16 deviations
   int trace_cap;
   int s_zero;        // criterion threshold is exactly zero
   float S;
@@ -50,16 +52,20 @@ struct Params {
   float psi_in[kMaxComp];
   float psi_rest[kMaxComp];
   float rho_rest[kMaxComp];
-  float f_in[kMaxComp][kQ];    // populations imposed by inlet nodes
-  float f_rest[kMaxComp][kQ];  // rest populations (bitwise fixed point)
+  float rho_ref_rest[kMaxComp];        // reference density of the stored rest state (FP16 store)
+  float f_in[kMaxComp][kQ];            // populations imposed by inlet nodes
+  float f_rest[kMaxComp][kQ];          // rest populations, decoded (bitwise fixed point)
+  uint32_t f_rest_bits[kMaxComp][kQ];  // rest populations in the stored format
 };
 
 // Device buffers of one handle.
+// A "plane" holds one value per cell of every slot: index slot*4096 + cell.
 struct Buffers {
-  float* f[2];            // populations, [(capacity+1)][ncomp][19][4096]
-  float* psi;             // [(capacity+1)][ncomp][4096]
-  uint32_t* mask;         // [(capacity+1)][4096]: bit i = link i bounces; kind in bits 24..25
-  float* uprev;           // [capacity][ncomp][3][4096] velocity of the previous step (criterion)
+  void* f[2];             // populations: [ncomp*19 planes] of float or __half
+  float* rho[2];          // FP16 store only: [ncomp planes] reference densities, double-buffered
+  float* psi;             // [ncomp planes] pseudo-potential of the current step
+  uint32_t* mask;         // [1 plane]: bit i = link i bounces; kind in bits 24..25
+  float* uprev;           // [ncomp*3 planes] velocity of the previous step (criterion; progressive only)
   int32_t* block_slot;    // [nb] slot of a block, -1 when inactive
   int32_t* slot_block;    // [capacity] block of a slot (the active list)
   uint8_t* bfluid;        // [nb] block holds a non-solid cell
@@ -75,7 +81,8 @@ struct Buffers {
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the
 // launch status.
 // Rest state: bg = device [2] background densities; out = device
-// [2*19 populations, 2 densities, 2 potentials]; iters = device int.
+// [2*19 stored bits][2*19 decoded populations][2 reference densities]
+// [2 densities][2 potentials]; iters = device int.
 hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream);
 hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first_slot_host, int count_host,
                              bool from_device_counts, bool use_initial_fields, hipStream_t stream);
@@ -83,6 +90,13 @@ hipError_t launch_moments(const Params& P, const Buffers& D, int rbuf, bool pull
                           hipStream_t stream);
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream);
 hipError_t launch_collide(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
+// Fused step kernel (moments, psi, forces, collision, streaming); the
+// frontier pass runs the blocks next to inactive blocks with the leak check.
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
+                        hipStream_t stream);
+// Criterion of Eq 13 on the shell cells of frontier blocks.
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
+                            hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
                          float* umix, hipStream_t stream);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,

@@ -2,11 +2,15 @@
 // pseudo-potential lattice Boltzmann update (Duchateau et al., arXiv
 // 1510.03560, sections 2 and 4).
 //
-// Data layout: the lattice is cut into 16^3 blocks; an active block owns a
-// slot of the pool.  Inside a slot everything is structure-of-arrays
-// (section 3): f[slot][comp][dir][cell] with cell = x + 16*(y + 16*z), so the
-// 64 lanes of a wave touch four consecutive x-rows, 256 contiguous bytes.
-// The extra slot `capacity` holds the rest state everywhere and stands in for
+// Data layout.  The lattice is cut into 16^3 blocks; an active block owns a
+// slot of the pool.  Populations are structure-of-arrays (section 3) by
+// (component, direction) plane over the whole pool:
+//     f[buf][plane = comp*19 + dir][slot*4096 + cell],  cell = x + 16*(y + 16*z)
+// so the 64 lanes of a wave read or write four consecutive x-rows of one
+// plane: 256 contiguous bytes (FP32).  Every pull is a 32-bit element index
+// from a wave-uniform base (the first plane of the opposite-direction pair),
+// which keeps address arithmetic in single VGPRs and lets both components
+// share it.  The extra slot `capacity` holds the rest state and stands in for
 // every inactive block and for the outside of the domain.
 //
 // One time step (section 4.3) runs
@@ -20,11 +24,17 @@
 // The state between steps is the post-collision f*; the first step of a run
 // reads the initial populations in place instead of pulling.
 //
+// Storage formats: FP32, or FP16 deviations h = s (f - w_i rho_ref) with
+// rho_ref the writing cell's own density of that step (kept, double-buffered,
+// in `rho`), s = 2^12; arithmetic is FP32 in both.
+//
 // Every floating-point expression is written out explicitly and the library
 // is compiled without floating-point contraction, so the same inputs give the
 // same bits in every kernel.  That makes the rest state computed by
 // k_rest_state an exact fixed point of k_moments + k_collide, which is what
 // lets a progressive run reproduce the static run bit for bit.
+
+#include <hip/hip_fp16.h>
 
 #include <type_traits>
 
@@ -32,6 +42,9 @@
 
 namespace lbm {
 namespace {
+
+constexpr int kThreads = 512;            // workgroup of the per-block kernels
+constexpr int kZStep = kThreads / 256;   // z-planes handled together
 
 // ----------------------------------------------------------------- lattice
 // D3Q19 (section 2.1, Fig 1b) with opposite directions adjacent: 2k-1 and 2k.
@@ -56,12 +69,45 @@ __host__ __device__ constexpr float dir_w(int i) {
 constexpr float kThird = 1.0f / 3.0f;
 
 template <int N, typename F>
-__device__ __forceinline__ void unroll(F&& fn) {
+__host__ __device__ __forceinline__ void unroll(F&& fn) {
   if constexpr (N > 0) {
     unroll<N - 1>(fn);
     fn(std::integral_constant<int, N - 1>{});
   }
 }
+
+// Loads and stores at a 32-bit byte offset from a wave-uniform base: the
+// form that keeps the base in SGPRs and the offset in one VGPR.  Offsets are
+// computed in 32-bit arithmetic by the callers (every population pair spans
+// less than 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// --------------------------------------------------------- storage codecs
+struct StoreF32 {
+  using T = float;
+  static constexpr bool kRef = false;
+  __device__ static __forceinline__ float decode(T v, float) { return v; }
+  __device__ static __forceinline__ T encode(float f, float) { return f; }
+  __device__ static __forceinline__ uint32_t bits(T v) { return __float_as_uint(v); }
+};
+
+// FP16 deviation from w_i rho_ref, scaled by 2^12 (wr = w_i * rho_ref).
+struct StoreF16 {
+  using T = __half;
+  static constexpr bool kRef = true;
+  static constexpr float kScale = 4096.0f;
+  static constexpr float kInvScale = 1.0f / 4096.0f;
+  __device__ static __forceinline__ float decode(T v, float wr) { return wr + __half2float(v) * kInvScale; }
+  __device__ static __forceinline__ T encode(float f, float wr) { return __float2half_rn((f - wr) * kScale); }
+  __device__ static __forceinline__ uint32_t bits(T v) { return (uint32_t)__half_as_ushort(v); }
+};
 
 // --------------------------------------------------------------- moments
 // Eq 4-5.  Momentum is accumulated over opposite pairs so that a population
@@ -110,50 +156,64 @@ __device__ __forceinline__ float pseudo_potential(const Params& P, int a, float 
 }
 
 // -------------------------------------------------------------- forcing
-// Stencil sum over opposite pairs: sum_i w_i v_i e_i with v_i the value at
-// x + e_i.  Exactly zero when v is uniform.
 struct Vec3 {
   float x, y, z;
 };
 
-__device__ __forceinline__ Vec3 pair_gradient(const float v[kQ]) {
-  const float a = 1.0f / 18.0f, d = 1.0f / 36.0f;
-  const float p1 = v[1] - v[2], p3 = v[3] - v[4], p5 = v[5] - v[6];
-  const float p7 = v[7] - v[8], p9 = v[9] - v[10], p11 = v[11] - v[12];
-  const float p13 = v[13] - v[14], p15 = v[15] - v[16], p17 = v[17] - v[18];
-  Vec3 s;
-  s.x = a * p1 + d * ((((p7 + p9) + p11) + p13));
-  s.y = a * p3 + d * ((((p7 - p9) + p15) + p17));
-  s.z = a * p5 + d * ((((p11 - p13) + p15) - p17));
-  return s;
-}
-
 // Eq 8-9 read with lattice weights (the paper's weights being 6 w_i):
 //   F_a = -beta g_aa psi_a(x) sum w_i psi_a(x+e_i) e_i
 //         - (1-beta)/2 g_aa sum w_i psi_a(x+e_i)^2 e_i
-//         - g_ab psi_a(x) sum w_i psi_b(x+e_i) e_i + rho_a body_a
-// nb_self[i] / nb_other[i]: psi of this / the other component at x + e_i,
+//         - g_ab psi_a(x) sum w_i psi_b(x+e_i) e_i
+// for every component at once (add_body adds rho_a body_a).  nb(a, i) returns psi of component a at x+e_i,
 // already replaced by the centre value where x + e_i is solid or outside.
-__device__ __forceinline__ Vec3 interaction_force(const Params& P, int a, float psi_c, const float nb_self[kQ],
-                                                  const float nb_other[kQ], float rho) {
-  float sq[kQ];
+// Stencil sums run over opposite pairs, so a uniform psi gives exactly zero.
+template <int NC, typename NB>
+__device__ __forceinline__ void interaction_forces(const Params& P, const float psi_c[NC], NB&& nb, Vec3 F[NC]) {
+  Vec3 s1[NC], s2[NC];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) sq[i] = nb_self[i] * nb_self[i];
-  const Vec3 s1 = pair_gradient(nb_self);
-  const Vec3 s2 = pair_gradient(sq);
-  const float c1 = -P.beta * P.g_self[a] * psi_c;
-  const float c2 = -0.5f * (1.0f - P.beta) * P.g_self[a];
-  Vec3 F;
-  F.x = c1 * s1.x + c2 * s2.x;
-  F.y = c1 * s1.y + c2 * s2.y;
-  F.z = c1 * s1.z + c2 * s2.z;
-  if (P.ncomp == 2) {
-    const Vec3 s3 = pair_gradient(nb_other);
-    const float c3 = -P.g_cross * psi_c;
-    F.x = F.x + c3 * s3.x;
-    F.y = F.y + c3 * s3.y;
-    F.z = F.z + c3 * s3.z;
+  for (int a = 0; a < NC; ++a) s1[a] = s2[a] = Vec3{0.0f, 0.0f, 0.0f};
+  unroll<9>([&](auto K) {
+    constexpr int i = 2 * decltype(K)::value + 1;  // pair (i, i+1), e_{i+1} = -e_i
+    constexpr int ex = dir_ex(i), ey = dir_ey(i), ez = dir_ez(i);
+    constexpr float w = dir_w(i);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const float p = nb(a, i), q = nb(a, i + 1);
+      const float d1 = w * (p - q);
+      const float d2 = d1 * (p + q);  // w (p^2 - q^2)
+      if constexpr (ex != 0) {
+        s1[a].x = ex > 0 ? s1[a].x + d1 : s1[a].x - d1;
+        s2[a].x = ex > 0 ? s2[a].x + d2 : s2[a].x - d2;
+      }
+      if constexpr (ey != 0) {
+        s1[a].y = ey > 0 ? s1[a].y + d1 : s1[a].y - d1;
+        s2[a].y = ey > 0 ? s2[a].y + d2 : s2[a].y - d2;
+      }
+      if constexpr (ez != 0) {
+        s1[a].z = ez > 0 ? s1[a].z + d1 : s1[a].z - d1;
+        s2[a].z = ez > 0 ? s2[a].z + d2 : s2[a].z - d2;
+      }
+    }
+  });
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    const float c1 = -P.beta * P.g_self[a] * psi_c[a];
+    const float c2 = -0.5f * (1.0f - P.beta) * P.g_self[a];
+    F[a].x = c1 * s1[a].x + c2 * s2[a].x;
+    F[a].y = c1 * s1[a].y + c2 * s2[a].y;
+    F[a].z = c1 * s1[a].z + c2 * s2[a].z;
+    if constexpr (NC == 2) {
+      const int b = 1 - a;
+      const float c3 = -P.g_cross * psi_c[a];
+      F[a].x = F[a].x + c3 * s1[b].x;
+      F[a].y = F[a].y + c3 * s1[b].y;
+      F[a].z = F[a].z + c3 * s1[b].z;
+    }
   }
+}
+
+// Extra body force per unit density (gravity, section 2.2), added last.
+__device__ __forceinline__ Vec3 add_body(const Params& P, int a, Vec3 F, float rho) {
   F.x = F.x + rho * P.body[a][0];
   F.y = F.y + rho * P.body[a][1];
   F.z = F.z + rho * P.body[a][2];
@@ -167,11 +227,14 @@ __device__ __forceinline__ Vec3 interaction_force(const Params& P, int a, float 
 // The forcing bracket is evaluated in its factored form
 //   w_i rho (3 e.du + 4.5 (e.du)(e.(u+v)) - 1.5 du.(u+v)),  v = u + du,
 // which is the same quantity without the cancellation of two equilibria.
+// Both are split over each opposite pair (e_j = -e_i) into a part even in e
+// (shared) and a part odd in e (sign flipped), which halves the work.
 // The collision conserves the cell's mass exactly, so the rest population is
 // taken as the remainder rho - sum_{i>0} f*_i: with FP32 weights (whose sum
 // exceeds 1 by 1.5e-8) the direct formula would add that much mass per step.
-__device__ __forceinline__ void collide(float omega, const float f[kQ], const Mom& m, const Vec3& F,
-                                        float out[kQ]) {
+template <typename Emit>
+__device__ __forceinline__ void collide_emit(float omega, const float f[kQ], const Mom& m, const Vec3& F,
+                                             Emit&& emit) {
   float inv = 0.0f;
   if (m.rho > 0.0f) inv = 1.0f / m.rho;
   const float ux = m.jx * inv, uy = m.jy * inv, uz = m.jz * inv;
@@ -179,27 +242,37 @@ __device__ __forceinline__ void collide(float omega, const float f[kQ], const Mo
   const float sx = (ux + ux) + dx, sy = (uy + uy) + dy, sz = (uz + uz) + dz;  // u + v
   const float usq = (ux * ux + uy * uy) + uz * uz;
   const float dus = (dx * sx + dy * sy) + dz * sz;
-  unroll<kQ>([&](auto I) {
-    constexpr int i = decltype(I)::value;
+  const float e0 = 1.0f - 1.5f * usq;  // even part of feq / (w rho), without (e.u)^2
+  const float d0 = -1.5f * dus;        // even part of the forcing bracket, without (e.du)(e.s)
+  // per weight class: w rho, 3 w rho, 4.5 w rho
+  const float wa = (1.0f / 18.0f) * m.rho, wd = (1.0f / 36.0f) * m.rho;
+  const float wa3 = 3.0f * wa, wd3 = 3.0f * wd, wa45 = 4.5f * wa, wd45 = 4.5f * wd;
+  const float wae = wa * e0, wde = wd * e0, wad = wa * d0, wdd = wd * d0;
+  float rest = 0.0f;
+  unroll<9>([&](auto K) {
+    constexpr int i = 2 * decltype(K)::value + 1, j = i + 1;
     constexpr int ex = dir_ex(i), ey = dir_ey(i), ez = dir_ez(i);
-    constexpr float w = dir_w(i);
+    constexpr bool axis = i <= 6;
+    const float w3 = axis ? wa3 : wd3, w45 = axis ? wa45 : wd45, we = axis ? wae : wde, wdv = axis ? wad : wdd;
     const float eu = float(ex) * ux + float(ey) * uy + float(ez) * uz;
     const float ed = float(ex) * dx + float(ey) * dy + float(ez) * dz;
     const float es = float(ex) * sx + float(ey) * sy + float(ez) * sz;
-    const float wr = w * m.rho;
-    const float feq = wr * (((1.0f + 3.0f * eu) + 4.5f * (eu * eu)) - 1.5f * usq);
-    const float df = wr * ((3.0f * ed + 4.5f * (ed * es)) - 1.5f * dus);
-    out[i] = (f[i] + omega * (feq - f[i])) + df;
+    const float even = we + w45 * (eu * eu);
+    const float odd = w3 * eu;
+    const float deven = wdv + w45 * (ed * es);
+    const float dodd = w3 * ed;
+    const float oi = (f[i] + omega * ((even + odd) - f[i])) + (deven + dodd);
+    const float oj = (f[j] + omega * ((even - odd) - f[j])) + (deven - dodd);
+    emit(std::integral_constant<int, i>{}, oi);
+    emit(std::integral_constant<int, j>{}, oj);
+    rest = i == 1 ? (oi + oj) : rest + (oi + oj);
   });
-  float rest = (out[1] + out[2]) + (out[3] + out[4]);
-  rest = rest + (out[5] + out[6]);
-  rest = rest + (out[7] + out[8]);
-  rest = rest + (out[9] + out[10]);
-  rest = rest + (out[11] + out[12]);
-  rest = rest + (out[13] + out[14]);
-  rest = rest + (out[15] + out[16]);
-  rest = rest + (out[17] + out[18]);
-  out[0] = m.rho - rest;
+  emit(std::integral_constant<int, 0>{}, m.rho - rest);
+}
+
+__device__ __forceinline__ void collide(float omega, const float f[kQ], const Mom& m, const Vec3& F,
+                                        float out[kQ]) {
+  collide_emit(omega, f, m, F, [&](auto I, float v) { out[decltype(I)::value] = v; });
 }
 
 __device__ __forceinline__ float feq_dir(int i, float rho, float ux, float uy, float uz) {
@@ -222,56 +295,104 @@ __device__ __forceinline__ int neighbour_block(const Params& P, int bx, int by, 
   return c[0] + P.nbx * (c[1] + P.nby * c[2]);
 }
 
-__device__ __forceinline__ int sgn_out(int s) { return s < 0 ? -1 : (s > 15 ? 1 : 0); }
+__host__ __device__ __forceinline__ int sgn_out(int s) { return s < 0 ? -1 : (s > 15 ? 1 : 0); }
 
-// Element index (within a population buffer, component 0) of the value that
-// streams into direction I of cell (x,y,z): f*_I(x - e_I), or f*_opp(I)(x)
-// when the link bounces (mask bit I).  nb[d] is the first element of the
-// slot of neighbour block d = 13 + ox + 3 oy + 9 oz.
-template <int I>
-__device__ __forceinline__ long long pull_index(int x, int y, int z, uint32_t m, const long long* nb) {
-  constexpr int ex = dir_ex(I), ey = dir_ey(I), ez = dir_ez(I);
-  if constexpr (I == 0) {
-    return nb[13] + (x + 16 * y + 256 * z);
-  } else {
-    const int sx = x - ex, sy = y - ey, sz = z - ez;
-    const int ox = ex ? sgn_out(sx) : 0, oy = ey ? sgn_out(sy) : 0, oz = ez ? sgn_out(sz) : 0;
-    const int c = (sx & 15) + 16 * (sy & 15) + 256 * (sz & 15);
-    const long long pulled = nb[13 + ox + 3 * oy + 9 * oz] + (long long)I * kCells + c;
-    const long long bounced = nb[13] + (long long)dir_opp(I) * kCells + (x + 16 * y + 256 * z);
-    return (m >> I) & 1u ? bounced : pulled;
-  }
+// Sources of the 19 populations arriving at a cell.  fidx[i] is the element
+// index of the value within the two planes of direction i's opposite pair
+// (plane offset included); for the FP16 store ridx[i] is the source cell's
+// index, where its reference density lives.  A bounced link (mask bit i:
+// x - e_i is solid or outside) reads the cell's own opposite population.
+template <bool REF>
+struct Sources {
+  uint32_t fidx[kQ];
+  uint32_t ridx[REF ? kQ : 1];
+};
+
+// Per-thread precomputation for the pulls.  For a shift s in {-1, 0, +1}
+// along an axis, the word (offset of the neighbour block along that axis,
+// scaled by 1, 3 or 9, in the high half) << 16 + (in-block coordinate of the
+// source, scaled by 1, 16 or 256) is stored, so that the sum of the three
+// words for a direction gives (neighbour index d << 16) + source cell in one
+// add: the low halves sum to at most 4095 and d lies in [0, 26].
+struct PullAxes {
+  uint32_t ax[3], ay[3], az[3];
+};
+
+__host__ __device__ __forceinline__ uint32_t pack_axis(int v, int shift, int scale_d, int scale_c, int bias) {
+  const int sv = v + shift;
+  const int o = sv < 0 ? -1 : (sv > 15 ? 1 : 0);
+  return ((uint32_t)(bias + scale_d * o) << 16) + (uint32_t)(scale_c * (sv & 15));
 }
 
-// Loads the 19 populations of component a arriving at (x,y,z).
-template <bool PULL>
-__device__ __forceinline__ void load_cell(const float* __restrict__ fb, long long comp_off, int x, int y, int z,
-                                          uint32_t m, const long long* nb, float f[kQ]) {
-  if constexpr (PULL) {
-    unroll<kQ>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      f[i] = fb[pull_index<i>(x, y, z, m, nb) + comp_off];
-    });
-  } else {
-    const long long base = nb[13] + comp_off + (x + 16 * y + 256 * z);
+__host__ __device__ __forceinline__ void pull_axes_xy(int x, int y, PullAxes& a) {
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[i] = fb[base + (long long)i * kCells];
+  for (int k = 0; k < 3; ++k) {
+    a.ax[k] = pack_axis(x, k - 1, 1, 1, 0);
+    a.ay[k] = pack_axis(y, k - 1, 3, 16, 0);
   }
+}
+__host__ __device__ __forceinline__ void pull_axes_z(int z, PullAxes& a) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a.az[k] = pack_axis(z, k - 1, 9, 256, 13);
+}
+
+template <bool PULL, bool REF>
+__host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t own, uint32_t m, uint32_t plane,
+                                        const int* nslot, Sources<REF>& s) {
+  s.fidx[0] = own;
+  if constexpr (REF) s.ridx[0] = own;
+  const uint32_t own_second = own + plane;
+  unroll<kQ - 1>([&](auto K) {
+    constexpr int i = decltype(K)::value + 1;
+    constexpr bool second = !(i & 1);  // plane i is the second of its pair
+    if constexpr (!PULL) {
+      s.fidx[i] = second ? own_second : own;
+      if constexpr (REF) s.ridx[i] = own;
+    } else {
+      constexpr int ex = dir_ex(i), ey = dir_ey(i), ez = dir_ez(i);
+      const uint32_t w = pa.ax[1 - ex] + pa.ay[1 - ey] + pa.az[1 - ez];  // source = x - e_i
+      const uint32_t src_cell = ((uint32_t)nslot[w >> 16] << 12) | (w & 0xFFFFu);
+      const bool bounce = (m >> i) & 1u;
+      // bounced: the cell's own population of the opposite direction, which
+      // is the other plane of the pair
+      s.fidx[i] = bounce ? (second ? own : own_second) : (second ? src_cell + plane : src_cell);
+      if constexpr (REF) s.ridx[i] = bounce ? own : src_cell;
+    }
+  });
+}
+
+// Populations of component a arriving at the cell (decoded to FP32).
+//   fb: buffer base; plane: elements per plane; rref: densities of the
+//   previous step (FP16 store only).
+template <typename S>
+__device__ __forceinline__ void gather(const typename S::T* __restrict__ fb, uint32_t plane, int a,
+                                       const Sources<S::kRef>& s, const float* __restrict__ rref, float f[kQ]) {
+  using T = typename S::T;
+  constexpr uint32_t sz = sizeof(T);
+  const T* base0 = fb + (size_t)(a * kQ) * plane;
+  const float* rbase = S::kRef ? rref + (size_t)a * plane : nullptr;
+  unroll<kQ>([&](auto K) {
+    constexpr int i = decltype(K)::value;
+    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);  // first plane of the pair
+    const T v = ld(base0 + (size_t)first * plane, s.fidx[i] * sz);
+    float wr = 0.0f;
+    if constexpr (S::kRef) wr = dir_w(i) * ld(rbase, s.ridx[i] * 4u);
+    f[i] = S::decode(v, wr);
+  });
 }
 
 // The 27 neighbour slots of a block (inactive and outside -> rest slot),
 // their block ids (-1 outside) and the candidate mask: neighbours that are
 // inside the domain, inactive and hold fluid.
 struct BlockCtx {
-  long long nb[27];
   int nslot[27];
   int nbk[27];
   unsigned cand;
   unsigned fired;
+  int has_bc;  // the block touches a face with inlet or outlet nodes
 };
 
-__device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, int blk, long long slot_elems,
-                                            BlockCtx& ctx) {
+__device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, int blk, BlockCtx& ctx) {
   const int t = threadIdx.x;
   const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
   bool cand = false;
@@ -281,7 +402,6 @@ __device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, i
     int sl = nbid < 0 ? -1 : D.block_slot[nbid];
     if (t != 13 && nbid >= 0 && sl < 0 && D.bfluid[nbid]) cand = true;
     if (sl < 0) sl = P.capacity;
-    ctx.nb[t] = (long long)sl * slot_elems;
     ctx.nslot[t] = sl;
     ctx.nbk[t] = nbid;
   }
@@ -290,6 +410,10 @@ __device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, i
   if (t == 0) {
     ctx.cand = (unsigned)bal;
     ctx.fired = 0u;
+    const bool on[6] = {bx == 0, bx == P.nbx - 1, by == 0, by == P.nby - 1, bz == 0, bz == P.nbz - 1};
+    int hb = 0;
+    for (int f = 0; f < 6; ++f) hb |= (on[f] && (P.bc[f] == kInletFace || P.bc[f] == kOutletFace)) ? 1 : 0;
+    ctx.has_bc = hb;
   }
 }
 
@@ -312,64 +436,115 @@ __device__ __forceinline__ unsigned shell_dirs(int x, int y, int z, int w) {
   return out & ~(1u << 13);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup g runs on
+// XCD g mod 8), and each XCD has its own L2.  Give XCD k the contiguous run of
+// slots [k*chunk, (k+1)*chunk): blocks next to each other in slot order (x
+// neighbours on the static mesh) then run together on one L2, and the cache
+// lines they share (the row that x-shifted pulls read from both sides) are
+// fetched once.  Grids are launched with a multiple of 8 workgroups.
+constexpr int kXcds = 8;
+// Returns n_active (no slot) for workgroups beyond the active range.
+__device__ __forceinline__ int slot_of_workgroup(int g, int n_active) {
+  const int chunk = (n_active + kXcds - 1) / kXcds;
+  const int q = g / kXcds;
+  if (q >= chunk) return n_active;
+  const int s = (g % kXcds) * chunk + q;
+  return s < n_active ? s : n_active;
+}
+__host__ __device__ constexpr int grid_for(int capacity) { return (capacity + kXcds - 1) / kXcds * kXcds; }
+
+template <typename S>
+__device__ __forceinline__ typename S::T* fplane(const Buffers& D, int buf) {
+  return reinterpret_cast<typename S::T*>(D.f[buf]);
+}
+
+// Stored form of the rest population of (a, i), from the bits the host
+// copied into Params.
+template <typename S>
+__device__ __forceinline__ typename S::T rest_stored(const Params& P, int a, int i) {
+  if constexpr (std::is_same<typename S::T, float>::value)
+    return __uint_as_float(P.f_rest_bits[a][i]);
+  else
+    return __ushort_as_half((unsigned short)P.f_rest_bits[a][i]);
+}
+
 // ----------------------------------------------------------- rest state
 // Iterates the update of a cell whose every neighbour is itself (uniform
-// lattice at rest, density bg) until the populations stop changing; the same
-// device functions as k_moments/k_collide, so the result is a fixed point of
-// the real update.  Single thread; tiny.
+// lattice at rest, density bg) until the stored populations (and, for the
+// FP16 store, the reference density) stop changing; the same device
+// functions as k_moments/k_collide, so the result is a fixed point of the
+// real update.  Single thread; tiny.
+//   out: [2*19] stored bits, then decoded populations [2*19], then
+//   reference density [2], density [2], psi [2] (as floats).
+template <typename S, int NC>
 __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  // the rest state is defined without body force
   for (int a = 0; a < kMaxComp; ++a) P.body[a][0] = P.body[a][1] = P.body[a][2] = 0.0f;
-  float f[kMaxComp][kQ];
-  for (int a = 0; a < P.ncomp; ++a)
-    for (int i = 0; i < kQ; ++i) f[a][i] = dir_w(i) * bg[a];
+  typename S::T h[NC][kQ];
+  float r[NC];
+  for (int a = 0; a < NC; ++a) {
+    r[a] = bg[a];
+    for (int i = 0; i < kQ; ++i) h[a][i] = S::encode(dir_w(i) * bg[a], dir_w(i) * r[a]);
+  }
   int it = 0;
   for (; it < 100000; ++it) {
-    float psi[kMaxComp] = {0.0f, 0.0f};
-    Mom m[kMaxComp];
-    for (int a = 0; a < P.ncomp; ++a) {
+    float f[NC][kQ], psi[NC], rho[NC];
+    Mom m[NC];
+    for (int a = 0; a < NC; ++a) {
+      for (int i = 0; i < kQ; ++i) f[a][i] = S::decode(h[a][i], dir_w(i) * r[a]);
       m[a] = moments(f[a]);
       bool cl;
       psi[a] = pseudo_potential(P, a, m[a].rho, cl);
+      rho[a] = m[a].rho;
     }
+    Vec3 F[NC];
+    interaction_forces<NC>(P, psi, [&](int a, int) { return psi[a]; }, F);
     bool same = true;
-    float nf[kMaxComp][kQ];
-    for (int a = 0; a < P.ncomp; ++a) {
-      float ns[kQ], no[kQ];
+    typename S::T nh[NC][kQ];
+    for (int a = 0; a < NC; ++a) {
+      float o[kQ];
+      collide(P.omega[a], f[a], m[a], add_body(P, a, F[a], rho[a]), o);
       for (int i = 0; i < kQ; ++i) {
-        ns[i] = psi[a];
-        no[i] = psi[P.ncomp == 2 ? 1 - a : a];
+        nh[a][i] = S::encode(o[i], dir_w(i) * m[a].rho);
+        same = same && (S::bits(nh[a][i]) == S::bits(h[a][i]));
       }
-      const Vec3 F = interaction_force(P, a, psi[a], ns, no, m[a].rho);
-      collide(P.omega[a], f[a], m[a], F, nf[a]);
-      for (int i = 0; i < kQ; ++i) same = same && (__float_as_uint(nf[a][i]) == __float_as_uint(f[a][i]));
+      same = same && (__float_as_uint(m[a].rho) == __float_as_uint(r[a]));
     }
-    for (int a = 0; a < P.ncomp; ++a)
-      for (int i = 0; i < kQ; ++i) f[a][i] = nf[a][i];
+    for (int a = 0; a < NC; ++a) {
+      r[a] = m[a].rho;
+      for (int i = 0; i < kQ; ++i) h[a][i] = nh[a][i];
+    }
     if (same) break;
   }
-  for (int a = 0; a < P.ncomp; ++a) {
-    const Mom m = moments(f[a]);
+  for (int a = 0; a < NC; ++a) {
+    float f[kQ];
+    for (int i = 0; i < kQ; ++i) {
+      f[i] = S::decode(h[a][i], dir_w(i) * r[a]);
+      out[a * kQ + i] = __uint_as_float(S::bits(h[a][i]));
+      out[kMaxComp * kQ + a * kQ + i] = f[i];
+    }
+    const Mom m = moments(f);
     bool cl;
-    for (int i = 0; i < kQ; ++i) out[a * kQ + i] = f[a][i];
-    out[kMaxComp * kQ + a] = m.rho;
-    out[kMaxComp * kQ + kMaxComp + a] = pseudo_potential(P, a, m.rho, cl);
+    out[4 * kQ + a] = r[a];
+    out[4 * kQ + kMaxComp + a] = m.rho;
+    out[4 * kQ + 2 * kMaxComp + a] = pseudo_potential(P, a, m.rho, cl);
   }
   *iters = it;
 }
 
 // ----------------------------------------------------------- slot init
 // Initialises slots [first, first+count): per-cell mask (links that bounce,
-// cell kind), populations of buffer `buf`, psi and the criterion history.
-// Slot `capacity` (the rest slot) is initialised the same way with the rest
-// state everywhere and an all-fluid mask.
+// cell kind), populations of buffer `buf`, psi, reference densities and the
+// criterion history.  Slot `capacity` (the rest slot) is initialised the same
+// way with the rest state everywhere and an all-fluid mask.
+template <typename S>
 __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int first_h, int count_h, int from_dev,
                                               int use_init) {
   const int first = from_dev ? D.ctrl[kNewFirst] : first_h;
   const int count = from_dev ? D.ctrl[kNewCount] : count_h;
-  const long long slot_elems = (long long)P.ncomp * kQ * kCells;
-  float* fb = D.f[buf];
+  const uint32_t plane = P.plane;
+  typename S::T* fb = fplane<S>(D, buf);
+  const long long N = (long long)P.nx * P.ny * P.nz;
   for (int k = blockIdx.x; k < count; k += gridDim.x) {
     const int slot = first + k;
     const bool rest_slot = slot == P.capacity;
@@ -378,6 +553,7 @@ __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int 
               bz = rest_slot ? 0 : blk / (P.nbx * P.nby);
     for (int c = threadIdx.x; c < kCells; c += blockDim.x) {
       const int x = c & 15, y = (c >> 4) & 15, z = c >> 8;
+      const uint32_t cid = (uint32_t)slot * kCells + c;
       uint32_t m = 0u;
       long long n = -1;
       if (!rest_slot) {
@@ -409,25 +585,32 @@ __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int 
           }
         });
       }
-      D.mask[(long long)slot * kCells + c] = m;
+      D.mask[cid] = m;
       for (int a = 0; a < P.ncomp; ++a) {
         float r0 = __int_as_float(0x7fc00000);  // NaN: rest state
         float ux = 0.0f, uy = 0.0f, uz = 0.0f;
         if (use_init && n >= 0 && D.init_rho) {
-          r0 = D.init_rho[(long long)a * P.nx * P.ny * P.nz + n];
+          r0 = D.init_rho[(long long)a * N + n];
           if (D.init_u) {
-            const long long N = (long long)P.nx * P.ny * P.nz;
             ux = D.init_u[n];
             uy = D.init_u[N + n];
             uz = D.init_u[2 * N + n];
           }
         }
         const bool at_rest = !(r0 == r0);
-        const long long base = (long long)slot * slot_elems + (long long)a * kQ * kCells + c;
-        for (int i = 0; i < kQ; ++i) fb[base + (long long)i * kCells] = at_rest ? P.f_rest[a][i] : feq_dir(i, r0, ux, uy, uz);
-        D.psi[((long long)slot * P.ncomp + a) * kCells + c] = P.psi_rest[a];
+        float fe[kQ];
+        for (int i = 0; i < kQ; ++i) fe[i] = at_rest ? 0.0f : feq_dir(i, r0, ux, uy, uz);
+        // reference density of the FP16 store: the cell's own density
+        const float rref = at_rest ? P.rho_ref_rest[a] : moments(fe).rho;
+        for (int i = 0; i < kQ; ++i)
+          fb[(size_t)(a * kQ + i) * plane + cid] = at_rest ? rest_stored<S>(P, a, i) : S::encode(fe[i], dir_w(i) * rref);
+        D.psi[(size_t)a * plane + cid] = P.psi_rest[a];
+        if constexpr (S::kRef) {
+          D.rho[0][(size_t)a * plane + cid] = rref;
+          D.rho[1][(size_t)a * plane + cid] = rref;
+        }
         if (!rest_slot && D.uprev)
-          for (int d = 0; d < 3; ++d) D.uprev[(((long long)slot * P.ncomp + a) * 3 + d) * kCells + c] = 0.0f;
+          for (int d = 0; d < 3; ++d) D.uprev[((size_t)(a * 3 + d)) * plane + cid] = 0.0f;
       }
     }
   }
@@ -435,34 +618,50 @@ __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int 
 
 // --------------------------------------------------------------- moments
 // K1: per active block, pull f(t), compute rho_a, u_a (Eq 4-5) and psi_a
-// (Eq 6-7) for every cell; store psi.  On frontier blocks (an inactive
-// neighbour holding fluid), evaluate Eq 13: a fluid cell within `shell` cells
-// of such a neighbour whose velocity differs from the previous step's, for
-// any component, requests that neighbour (section 4.2).  crit_mode: 0 = no
-// criterion, 1 = only record velocities (first step), 2 = evaluate and record.
-template <bool PULL>
-__global__ void __launch_bounds__(256) k_moments(Params P, Buffers D, int rbuf, int crit_mode) {
-  const int s = blockIdx.x;
-  if (s >= D.ctrl[kNActive]) return;
+// (Eq 6-7) for every cell; store psi (and, for the FP16 store, rho as the
+// next reference).  On frontier blocks (an inactive neighbour holding fluid),
+// evaluate Eq 13: a fluid cell within `shell` cells of such a neighbour whose
+// velocity differs from the previous step's, for any component, requests
+// that neighbour (section 4.2).  crit_mode: 0 = no criterion, 1 = only record
+// velocities (first step), 2 = evaluate and record.
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_moments(Params P, Buffers D, int rbuf, int crit_mode) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
   __shared__ BlockCtx ctx;
-  const long long slot_elems = (long long)P.ncomp * kQ * kCells;
-  setup_block(P, D, D.slot_block[s], slot_elems, ctx);
+  setup_block(P, D, D.slot_block[s], ctx);
   __syncthreads();
   const unsigned cand = crit_mode ? ctx.cand : 0u;
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  const float* __restrict__ fb = D.f[rbuf];
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
+  const uint32_t plane = P.plane;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // densities of the previous step
+  float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;
+  const uint32_t own_base = (uint32_t)s * kCells;
   unsigned fired = 0u;
   unsigned numeric = 0u, clamps = 0u;
-  for (int z = 0; z < kB; ++z) {
-    const int c = x + 16 * y + 256 * z;
-    const uint32_t m = D.mask[(long long)s * kCells + c];
+#pragma unroll 1
+  for (int z = z0; z < kB; z += kZStep) {
+    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t m = ld(D.mask, cid * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
+    // solid cells have no populations to pull; their psi is never read (a
+    // solid neighbour contributes the centre's own psi)
+    if (kind == kSolid) continue;
+    Sources<S::kRef> src;
+    pull_axes_z(z, pa);
+    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    float f[NC][kQ];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) gather<S>(fb, plane, a, src, rref, f[a]);
     const unsigned dirs = cand ? (shell_dirs(x, y, z, P.shell) & cand) : 0u;
     bool changed = false;
-    for (int a = 0; a < P.ncomp; ++a) {
-      float f[kQ];
-      load_cell<PULL>(fb, (long long)a * kQ * kCells, x, y, z, m, ctx.nb, f);
-      const Mom mo = moments(f);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const Mom mo = moments(f[a]);
       float psi = 0.0f;
       if (kind == kFluid) {
         bool cl;
@@ -474,23 +673,24 @@ __global__ void __launch_bounds__(256) k_moments(Params P, Buffers D, int rbuf, 
       } else if (kind == kOutlet) {
         psi = P.psi_rest[a];
       }
-      D.psi[((long long)s * P.ncomp + a) * kCells + c] = psi;
+      st(D.psi + (size_t)a * plane, cid * 4u, psi);
+      if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, mo.rho);
       if (dirs && kind != kSolid) {
         float inv = 0.0f;
         if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
         const float u[3] = {mo.jx * inv, mo.jy * inv, mo.jz * inv};
-        float* up = D.uprev + (((long long)s * P.ncomp + a) * 3) * kCells + c;
+        float* up = D.uprev + (size_t)(a * 3) * plane + cid;
         if (crit_mode == 2) {
           float d2 = 0.0f;
           bool diff = false;
           for (int d = 0; d < 3; ++d) {
-            const float dd = u[d] - up[(long long)d * kCells];
+            const float dd = u[d] - up[(size_t)d * plane];
             diff = diff || (dd != 0.0f);
             d2 = d2 + dd * dd;
           }
           changed = changed || (P.s_zero ? diff : (sqrtf(d2) > P.S));
         }
-        for (int d = 0; d < 3; ++d) up[(long long)d * kCells] = u[d];
+        for (int d = 0; d < 3; ++d) up[(size_t)d * plane] = u[d];
       }
     }
     if (changed) fired |= dirs;
@@ -575,100 +775,496 @@ constexpr int kHalo = kH * kH * kH;   // 5832 cells
 
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x + 1) + kH * ((y + 1) + kH * (z + 1)); }
 
-template <bool PULL, int MODE>
-__global__ void __launch_bounds__(256) k_collide(Params P, Buffers D, int rbuf, float* dbg_psi, float* dbg_force) {
-  const int s = blockIdx.x;
-  if (s >= D.ctrl[kNActive]) return;
+template <typename S, int NC, bool PULL, int MODE>
+__global__ void __launch_bounds__(kThreads) k_collide(Params P, Buffers D, int rbuf, float* dbg_psi,
+                                                       float* dbg_force) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
   __shared__ BlockCtx ctx;
-  __shared__ float psi_s[kMaxComp * kHalo];
-  const long long slot_elems = (long long)P.ncomp * kQ * kCells;
+  __shared__ float psi_s[NC * kHalo];
+  __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
+  __shared__ uint32_t f_rest_bits_s[NC][kQ];
   const int blk = D.slot_block[s];
-  setup_block(P, D, blk, slot_elems, ctx);
+  setup_block(P, D, blk, ctx);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
+    const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
+    f_in_s[a][i] = P.f_in[a][i];
+    f_rest_s[a][i] = P.f_rest[a][i];
+    f_rest_bits_s[a][i] = P.f_rest_bits[a][i];
+  }
   __syncthreads();
-  // psi halo
+  const uint32_t plane = P.plane;
   for (int h = threadIdx.x; h < kHalo; h += blockDim.x) {
     const int hx = h % kH - 1, hy = (h / kH) % kH - 1, hz = h / (kH * kH) - 1;
     const int d = 13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(hz);
-    const long long slot = ctx.nslot[d];
-    const int c = (hx & 15) + 16 * (hy & 15) + 256 * (hz & 15);
-    for (int a = 0; a < P.ncomp; ++a) psi_s[a * kHalo + h] = D.psi[(slot * P.ncomp + a) * kCells + c];
+    const uint32_t cid = (uint32_t)ctx.nslot[d] * kCells + (uint32_t)((hx & 15) + 16 * (hy & 15) + 256 * (hz & 15));
+#pragma unroll
+    for (int a = 0; a < NC; ++a) psi_s[a * kHalo + h] = ld(D.psi + (size_t)a * plane, cid * 4u);
   }
   __syncthreads();
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  const float* __restrict__ fb = D.f[rbuf];
-  float* __restrict__ fw = D.f[rbuf ^ 1];
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  typename S::T* __restrict__ fw = fplane<S>(D, rbuf ^ 1);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;      // references of f(t)
+  const float* __restrict__ rcur = S::kRef ? D.rho[rbuf ^ 1] : nullptr;  // this step's densities
   const bool frontier = ctx.cand != 0u;
-  unsigned long long leak = 0ull;
-  const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
-  for (int z = 0; z < kB; ++z) {
-    const int c = x + 16 * y + 256 * z;
-    const uint32_t m = D.mask[(long long)s * kCells + c];
-    const uint32_t kind = (m >> kKindShift) & 3u;
-    if (kind == kSolid) continue;
-    const int h0 = hidx(x, y, z);
-    bool bad_psi = false;
-    for (int a = 0; a < P.ncomp; ++a) bad_psi = bad_psi || (psi_s[a * kHalo + h0] != P.psi_rest[a]);
-    uint32_t bad_dirs = 0u;
-    for (int a = 0; a < P.ncomp; ++a) {
-      const int o = P.ncomp == 2 ? 1 - a : a;
-      const float pc = psi_s[a * kHalo + h0], po = psi_s[o * kHalo + h0];
-      float f[kQ];
-      load_cell<PULL>(fb, (long long)a * kQ * kCells, x, y, z, m, ctx.nb, f);
-      const Mom mo = moments(f);
-      float out[kQ];
-      Vec3 F = {0.0f, 0.0f, 0.0f};
-      if (kind == kFluid) {
-        float ns[kQ], no[kQ];
-        ns[0] = pc;
-        no[0] = po;
-        unroll<kQ>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (i > 0) {
-            const int hn = hidx(x + dir_ex(i), y + dir_ey(i), z + dir_ez(i));
-            const bool solid_nb = (m >> dir_opp(i)) & 1u;  // x + e_i is solid or outside
-            ns[i] = solid_nb ? pc : psi_s[a * kHalo + hn];
-            no[i] = solid_nb ? po : psi_s[o * kHalo + hn];
-          }
-        });
-        F = interaction_force(P, a, pc, ns, no, mo.rho);
-        if constexpr (MODE == 0) collide(P.omega[a], f, mo, F, out);
-      } else {
-        const float* src = kind == kInlet ? P.f_in[a] : P.f_rest[a];
+  const uint32_t own_base = (uint32_t)s * kCells;
+  // Stores value v of population (a, i) of cell cid in the storage format.
+  auto emit = [&](uint32_t cid, int a, auto I, float v, float rr) {
+    constexpr int i = decltype(I)::value;
+    // plane i addressed from the first plane of its opposite pair
+    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+    constexpr bool second = i != 0 && !(i & 1);
+    const uint32_t off = (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T);
+    st(fw + (size_t)(a * kQ + first) * plane, off, S::encode(v, dir_w(i) * rr));
+  };
+  // reference density of the FP16 store: this cell's density of this step
+  auto ref_of = [&](uint32_t cid, int a) -> float {
+    if constexpr (S::kRef) return ld(rcur + (size_t)a * plane, cid * 4u);
+    return 0.0f;
+  };
+  if constexpr (MODE == 0) {
+    // fluid cells: pull, forces, collision, store
+#pragma unroll 1
+    for (int z = z0; z < kB; z += kZStep) {
+      const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+      const uint32_t m = ld(D.mask, cid * 4u);
+      if (((m >> kKindShift) & 3u) != kFluid) continue;
+      const int h0 = hidx(x, y, z);
+      float psi_c[NC];
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) out[i] = src[i];
-      }
-      if constexpr (MODE == 0) {
-        const long long wb = (long long)s * slot_elems + (long long)a * kQ * kCells + c;
+      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[a * kHalo + h0];
+      Sources<S::kRef> src;
+      pull_axes_z(z, pa);
+      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+      // forces of every component first: they need only psi
+      Vec3 F[NC];
+      interaction_forces<NC>(P, psi_c,
+                             [&](int a, int i) {
+                               const int hn = h0 + dir_ex(i) + kH * (dir_ey(i) + kH * dir_ez(i));
+                               const bool solid_nb = (m >> dir_opp(i)) & 1u;  // x + e_i solid or outside
+                               return solid_nb ? psi_c[a] : psi_s[a * kHalo + hn];
+                             },
+                             F);
+      // then one component at a time: pull, collide, store (the barrier keeps
+      // the next component's loads below these stores)
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) fw[wb + (long long)i * kCells] = out[i];
-        if (frontier) {
-          // leak check toward cells of inactive blocks
-          unroll<kQ>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0) {
-              const int tx = x + dir_ex(i), ty = y + dir_ey(i), tz = z + dir_ez(i);
-              const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
-              const bool outside_or_solid = (m >> dir_opp(i)) & 1u;
-              const bool inactive = ctx.nslot[d] == P.capacity && d != 13;
-              if (!outside_or_solid && inactive && (out[i] != P.f_rest[a][i] || bad_psi)) bad_dirs |= 1u << i;
-            }
-          });
-        }
-      } else {
-        const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
-        const long long N = (long long)P.nx * P.ny * P.nz;
-        const long long n = X + (long long)P.nx * (Y + (long long)P.ny * Z);
-        dbg_psi[a * N + n] = pc;
-        dbg_force[(a * 3 + 0) * N + n] = F.x;
-        dbg_force[(a * 3 + 1) * N + n] = F.y;
-        dbg_force[(a * 3 + 2) * N + n] = F.z;
+      for (int a = 0; a < NC; ++a) {
+        if (a > 0) __builtin_amdgcn_sched_barrier(0);
+        float f[kQ];
+        gather<S>(fb, plane, a, src, rref, f);
+        const Mom mo = moments(f);
+        const float rr = ref_of(cid, a);
+        collide_emit(P.omega[a], f, mo, add_body(P, a, F[a], mo.rho),
+                     [&](auto I, float v) { emit(cid, a, I, v, rr); });
       }
     }
-    leak += (unsigned long long)__popc(bad_dirs);
+    // boundary nodes impose their state (only blocks on an inlet/outlet face)
+    if (ctx.has_bc) {
+#pragma unroll 1
+      for (int z = z0; z < kB; z += kZStep) {
+        const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+        const uint32_t kind = (ld(D.mask, cid * 4u) >> kKindShift) & 3u;
+        if (kind != kInlet && kind != kOutlet) continue;
+        for (int a = 0; a < NC; ++a) {
+          const float rr = ref_of(cid, a);
+          unroll<kQ>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            emit(cid, a, I, kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], rr);
+          });
+        }
+      }
+    }
+    // Leak check (blocks next to an inactive block): what each cell handed
+    // to a cell of an inactive block must be the rest state, in the stored
+    // format a reader would see.  Reads back this thread's own stores.
+    if (frontier) {
+      unsigned long long leak = 0ull;
+#pragma unroll 1
+      for (int z = z0; z < kB; z += kZStep) {
+        const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+        const uint32_t m = ld(D.mask, cid * 4u);
+        if (((m >> kKindShift) & 3u) == kSolid) continue;
+        if (x > 0 && x < 15 && y > 0 && y < 15 && z > 0 && z < 15) continue;
+        const int h0 = hidx(x, y, z);
+        bool bad_cell = false;
+        for (int a = 0; a < NC; ++a) {
+          bad_cell = bad_cell || (psi_s[a * kHalo + h0] != P.psi_rest[a]);
+          if constexpr (S::kRef) bad_cell = bad_cell || (ref_of(cid, a) != P.rho_ref_rest[a]);
+        }
+        uint32_t bad_dirs = 0u;
+        unroll<kQ - 1>([&](auto I) {
+          constexpr int i = decltype(I)::value + 1;
+          constexpr int first = (i & 1) ? i : i - 1;
+          constexpr bool second = !(i & 1);
+          const int tx = x + dir_ex(i), ty = y + dir_ey(i), tz = z + dir_ez(i);
+          const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
+          const bool outside_or_solid = (m >> dir_opp(i)) & 1u;
+          if (d != 13 && ctx.nslot[d] == P.capacity && !outside_or_solid) {
+            bool differs = bad_cell;
+            for (int a = 0; a < NC; ++a) {
+              const uint32_t off = (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T);
+              const typename S::T v = ld(fw + (size_t)(a * kQ + first) * plane, off);
+              differs = differs || (S::bits(v) != f_rest_bits_s[a][i]);
+            }
+            if (differs) bad_dirs |= 1u << i;
+          }
+        });
+        leak += (unsigned long long)__popc(bad_dirs);
+      }
+      if (leak) atomicAdd(&D.counters[0], leak);
+    }
+  } else {
+    // debug: psi and the total force of every fluid cell
+    const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
+    const long long N = (long long)P.nx * P.ny * P.nz;
+#pragma unroll 1
+    for (int z = z0; z < kB; z += kZStep) {
+      const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+      const uint32_t m = ld(D.mask, cid * 4u);
+      const uint32_t kind = (m >> kKindShift) & 3u;
+      if (kind == kSolid) continue;
+      const int h0 = hidx(x, y, z);
+      float psi_c[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[a * kHalo + h0];
+      Vec3 F[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) F[a] = Vec3{0.0f, 0.0f, 0.0f};
+      if (kind == kFluid)
+        interaction_forces<NC>(P, psi_c,
+                               [&](int a, int i) {
+                                 const int hn = h0 + dir_ex(i) + kH * (dir_ey(i) + kH * dir_ez(i));
+                                 const bool solid_nb = (m >> dir_opp(i)) & 1u;
+                                 return solid_nb ? psi_c[a] : psi_s[a * kHalo + hn];
+                               },
+                               F);
+      Sources<S::kRef> src;
+      pull_axes_z(z, pa);
+      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+      const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        float f[kQ];
+        gather<S>(fb, plane, a, src, rref, f);
+        const Vec3 Fa = kind == kFluid ? add_body(P, a, F[a], moments(f).rho) : F[a];
+        dbg_psi[a * N + n] = psi_c[a];
+        dbg_force[(a * 3 + 0) * N + n] = Fa.x;
+        dbg_force[(a * 3 + 1) * N + n] = Fa.y;
+        dbg_force[(a * 3 + 2) * N + n] = Fa.z;
+      }
+    }
   }
-  if constexpr (MODE == 0) {
-    if (frontier && leak) atomicAdd(&D.counters[0], leak);
+}
+
+// ------------------------------------------------------------ fused step
+// The production step kernel: moments, pseudo-potential, forces, collision
+// and streaming in one pass over the populations.  One workgroup per active
+// block.  Thread t owns a column of the block's 18 x 18 footprint (the block
+// plus a one-cell ring): t < 256 the 16 x 16 interior (four full waves,
+// coalesced rows), 256 <= t < 324 the ring.  The workgroup sweeps the planes
+// z = -1 .. 16.  At plane z every column pulls its cell's populations,
+// computes rho and psi (Eq 4-7) and puts psi in a ring of four LDS planes;
+// after one barrier the interior threads collide their cell of plane z - 1
+// (forces from the three LDS planes z-2 .. z, Eq 8-12) with the populations
+// they pulled one plane earlier and still hold in registers, and store f*.
+// Cells of inactive blocks (and outside the domain) are frozen at the rest
+// state: they contribute psi_rest without being pulled.  Psi never goes to
+// memory; the populations are read once (plus the ring and the two halo
+// planes, which neighbouring blocks also read) and written once.
+// Boundary nodes impose their state in a post-pass (blocks on an inlet or
+// outlet face only).  LEAK instantiations run on frontier blocks only (the
+// others exit) and count what a cell hands to a cell of an inactive block.
+constexpr int kFusedThreads = 384;
+constexpr int kPsiRing = 4;
+constexpr int kFoot = kH * kH;  // 324 columns
+
+template <typename S, int NC, bool PULL, bool LEAK>
+__global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, int rbuf) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
+  __shared__ BlockCtx ctx;
+  __shared__ float psi_s[kPsiRing][NC][kFoot];
+  __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
+  __shared__ uint32_t f_rest_bits_s[NC][kQ];
+  setup_block(P, D, D.slot_block[s], ctx);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
+    const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
+    f_in_s[a][i] = P.f_in[a][i];
+    f_rest_s[a][i] = P.f_rest[a][i];
+    f_rest_bits_s[a][i] = P.f_rest_bits[a][i];
   }
+  __syncthreads();
+  if ((ctx.cand != 0u) != LEAK) return;  // uniform: frontier blocks run the LEAK variant
+  const int t = threadIdx.x;
+  const bool col = t < kFoot;
+  const bool interior = t < 256;
+  int cx, cy;
+  if (interior) {
+    cx = t & 15;
+    cy = t >> 4;
+  } else {
+    const int r = col ? t - 256 : 0;  // ring: rows y = -1, 16 (18 each), then columns x = -1, 16
+    if (r < 18) {
+      cx = r - 1;
+      cy = -1;
+    } else if (r < 36) {
+      cx = r - 19;
+      cy = 16;
+    } else if (r < 52) {
+      cx = -1;
+      cy = r - 36;
+    } else {
+      cx = 16;
+      cy = r - 52;
+    }
+  }
+  const int hp = (cy + 1) * kH + (cx + 1);  // index in an LDS psi plane
+  PullAxes pa;
+  pull_axes_xy(cx, cy, pa);
+  const int dxy = 13 + sgn_out(cx) + 3 * sgn_out(cy);
+  const uint32_t cxy = (uint32_t)((cx & 15) + 16 * (cy & 15));
+  const uint32_t plane = P.plane;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  typename S::T* __restrict__ fw = fplane<S>(D, rbuf ^ 1);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;   // references of f(t)
+  float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;     // this step's densities
+  const uint32_t own_base = (uint32_t)s * kCells;
+  float fp[NC][kQ];   // populations of this column's cell one plane back
+  float rp[NC];       // and its densities
+  uint32_t mp = 0u;   // and its mask
+  bool collide_next = false;
+  unsigned numeric = 0u, clamps = 0u;
+  unsigned long long leak = 0ull;
+#pragma unroll 1
+  for (int k = 0; k < kH; ++k) {
+    const int z = k - 1;
+    // ---- plane z: pull, moments, psi
+    float f[NC][kQ];
+    float rho[NC];
+    uint32_t m = 0u;
+    bool fluid = false;
+    if (col) {
+      float psi[NC];
+      const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
+      const uint32_t cell = (uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15);
+      const bool own = interior && z >= 0 && z < kB;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) psi[a] = P.psi_rest[a];
+      if (slot != P.capacity) {
+        m = ld(D.mask, cell * 4u);
+        const uint32_t kind = (m >> kKindShift) & 3u;
+        if (kind == kFluid) {
+          fluid = true;
+          Sources<S::kRef> src;
+          pull_axes_z(z, pa);
+          sources<PULL, S::kRef>(pa, cell, m, plane, ctx.nslot, src);
+#pragma unroll
+          for (int a = 0; a < NC; ++a) {
+            gather<S>(fb, plane, a, src, rref, f[a]);
+            rho[a] = moments(f[a]).rho;
+            bool cl;
+            psi[a] = pseudo_potential(P, a, rho[a], cl);
+            if (own) {
+              clamps += cl ? 1u : 0u;
+              if (!(rho[a] > 0.0f && rho[a] < 3.0e38f)) numeric = 1u;
+            }
+          }
+        } else if (kind == kInlet) {
+#pragma unroll
+          for (int a = 0; a < NC; ++a) psi[a] = P.psi_in[a];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) psi_s[k % kPsiRing][a][hp] = psi[a];
+    }
+    __syncthreads();
+    // ---- plane z - 1: forces, collision, store (interior fluid cells)
+    if (collide_next) {
+      const int zc = z - 1;
+      const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * zc);
+      const int sl[3] = {(k + 2) % kPsiRing, (k + 3) % kPsiRing, k % kPsiRing};  // planes zc-1, zc, zc+1
+      float psi_c[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[sl[1]][a][hp];
+      Vec3 F[NC];
+      interaction_forces<NC>(P, psi_c,
+                             [&](int a, int i) {
+                               const int hn = hp + dir_ex(i) + kH * dir_ey(i);
+                               const bool solid_nb = (mp >> dir_opp(i)) & 1u;  // x + e_i solid or outside
+                               return solid_nb ? psi_c[a] : psi_s[sl[1 + dir_ez(i)]][a][hn];
+                             },
+                             F);
+      bool bad_psi = false;
+      if constexpr (LEAK) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) bad_psi = bad_psi || (psi_c[a] != P.psi_rest[a]);
+      }
+      uint32_t bad_dirs = 0u;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        Mom mo = moments(fp[a]);
+        const float rr = rp[a];  // FP16 reference: this cell's density of this step
+        if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
+        const bool bad_ref = S::kRef && (rr != P.rho_ref_rest[a]);
+        collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho), [&](auto I, float v) {
+          constexpr int i = decltype(I)::value;
+          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+          constexpr bool second = i != 0 && !(i & 1);
+          const typename S::T enc = S::encode(v, dir_w(i) * rr);
+          st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+          if constexpr (LEAK && i > 0) {
+            const int tx = cx + dir_ex(i), ty = cy + dir_ey(i), tz = zc + dir_ez(i);
+            const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
+            const bool outside_or_solid = (mp >> dir_opp(i)) & 1u;
+            const bool inactive = d != 13 && ctx.nslot[d] == P.capacity;
+            const bool differs = S::bits(enc) != f_rest_bits_s[a][i] || bad_ref || bad_psi;
+            if (!outside_or_solid && inactive && differs) bad_dirs |= 1u << i;
+          }
+        });
+      }
+      if constexpr (LEAK) leak += (unsigned long long)__popc(bad_dirs);
+    }
+    // ---- keep plane z for its collision at the next iteration
+    collide_next = interior && fluid && z >= 0 && z < kB;
+    if (collide_next) {
+      mp = m;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        rp[a] = rho[a];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) fp[a][i] = f[a][i];
+      }
+    }
+  }
+  // ---- boundary nodes impose their state (blocks on an inlet/outlet face)
+  if (ctx.has_bc && interior) {
+    PullAxes pb = pa;
+#pragma unroll 1
+    for (int z = 0; z < kB; ++z) {
+      const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * z);
+      const uint32_t m = ld(D.mask, cid * 4u);
+      const uint32_t kind = (m >> kKindShift) & 3u;
+      if (kind != kInlet && kind != kOutlet) continue;
+      float rr[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) rr[a] = 0.0f;
+      if constexpr (S::kRef) {
+        // the reference is the node's own density of this step
+        Sources<S::kRef> src;
+        pull_axes_z(z, pb);
+        sources<PULL, S::kRef>(pb, cid, m, plane, ctx.nslot, src);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          float f[kQ];
+          gather<S>(fb, plane, a, src, rref, f);
+          rr[a] = moments(f).rho;
+          st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
+        }
+      }
+      bool bad_cell = false;
+      if constexpr (LEAK) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          bad_cell = bad_cell || (kind == kInlet ? P.psi_in[a] : P.psi_rest[a]) != P.psi_rest[a];
+          if constexpr (S::kRef) bad_cell = bad_cell || (rr[a] != P.rho_ref_rest[a]);
+        }
+      }
+      uint32_t bad_dirs = 0u;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        unroll<kQ>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+          constexpr bool second = i != 0 && !(i & 1);
+          const typename S::T enc = S::encode(kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], dir_w(i) * rr[a]);
+          st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+          if constexpr (LEAK && i > 0) {
+            const int tx = cx + dir_ex(i), ty = cy + dir_ey(i), tz = z + dir_ez(i);
+            const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
+            const bool outside_or_solid = (m >> dir_opp(i)) & 1u;
+            const bool inactive = d != 13 && ctx.nslot[d] == P.capacity;
+            if (!outside_or_solid && inactive && (S::bits(enc) != f_rest_bits_s[a][i] || bad_cell))
+              bad_dirs |= 1u << i;
+          }
+        });
+      }
+      if constexpr (LEAK) leak += (unsigned long long)__popc(bad_dirs);
+    }
+  }
+  if (numeric) atomicOr(&D.ctrl[kNumeric], 1);
+  if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
+  if constexpr (LEAK) {
+    if (leak) atomicAdd(&D.counters[0], leak);
+  }
+}
+
+// ------------------------------------------------------------- criterion
+// Eq 13 on frontier blocks only (section 4.2): a fluid cell within `shell`
+// cells of an inactive neighbour block that holds fluid, whose velocity
+// differs from the previous step's for any component, requests that block.
+// Only the shell cells of frontier blocks are pulled, so once the mesh covers
+// the domain this kernel does no work.  crit_mode 1 only records velocities.
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kThreads) k_criterion(Params P, Buffers D, int rbuf, int crit_mode) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
+  __shared__ BlockCtx ctx;
+  setup_block(P, D, D.slot_block[s], ctx);
+  __syncthreads();
+  const unsigned cand = ctx.cand;
+  if (!cand) return;  // uniform
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
+  const uint32_t plane = P.plane;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
+  const uint32_t own_base = (uint32_t)s * kCells;
+  unsigned fired = 0u;
+#pragma unroll 1
+  for (int z = z0; z < kB; z += kZStep) {
+    const unsigned dirs = shell_dirs(x, y, z, P.shell) & cand;
+    if (!dirs) continue;
+    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t m = ld(D.mask, cid * 4u);
+    if (((m >> kKindShift) & 3u) == kSolid) continue;
+    Sources<S::kRef> src;
+    pull_axes_z(z, pa);
+    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    bool changed = false;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      float f[kQ];
+      gather<S>(fb, plane, a, src, rref, f);
+      const Mom mo = moments(f);
+      float inv = 0.0f;
+      if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
+      const float u[3] = {mo.jx * inv, mo.jy * inv, mo.jz * inv};
+      float* up = D.uprev + (size_t)(a * 3) * plane + cid;
+      if (crit_mode == 2) {
+        float d2 = 0.0f;
+        bool diff = false;
+        for (int d = 0; d < 3; ++d) {
+          const float dd = u[d] - up[(size_t)d * plane];
+          diff = diff || (dd != 0.0f);
+          d2 = d2 + dd * dd;
+        }
+        changed = changed || (P.s_zero ? diff : (sqrtf(d2) > P.S));
+      }
+      for (int d = 0; d < 3; ++d) up[(size_t)d * plane] = u[d];
+    }
+    if (changed) fired |= dirs;
+  }
+  if (fired) atomicOr(&ctx.fired, fired);
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 27 && ((ctx.fired >> t) & 1u)) D.request[ctx.nbk[t]] = 1;
 }
 
 // ---------------------------------------------------------------- export
@@ -688,29 +1284,41 @@ __global__ void k_fill_default(Params P, Buffers D, float* rho, float* u, float*
 }
 
 // Moments (Eq 4-5) of the active blocks into lattice-wide arrays.
-template <bool PULL>
-__global__ void __launch_bounds__(256) k_export(Params P, Buffers D, int rbuf, float* rho, float* u, float* umix) {
-  const int s = blockIdx.x;
-  if (s >= D.ctrl[kNActive]) return;
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rbuf, float* rho, float* u,
+                                                      float* umix) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
   __shared__ BlockCtx ctx;
-  const long long slot_elems = (long long)P.ncomp * kQ * kCells;
   const int blk = D.slot_block[s];
-  setup_block(P, D, blk, slot_elems, ctx);
+  setup_block(P, D, blk, ctx);
   __syncthreads();
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
   const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
   const long long N = (long long)P.nx * P.ny * P.nz;
-  for (int z = 0; z < kB; ++z) {
-    const int c = x + 16 * y + 256 * z;
-    const uint32_t m = D.mask[(long long)s * kCells + c];
+  const uint32_t plane = P.plane;
+  const uint32_t own_base = (uint32_t)s * kCells;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
+#pragma unroll 1
+  for (int z = z0; z < kB; z += kZStep) {
+    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t m = D.mask[cid];
     const bool sol = ((m >> kKindShift) & 3u) == kSolid;
     const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
     float mr = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
-    for (int a = 0; a < P.ncomp; ++a) {
+    Sources<S::kRef> src;
+    pull_axes_z(z, pa);
+    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
       Mom mo = {0.0f, 0.0f, 0.0f, 0.0f};
       if (!sol) {
         float f[kQ];
-        load_cell<PULL>(D.f[rbuf], (long long)a * kQ * kCells, x, y, z, m, ctx.nb, f);
+        gather<S>(fb, plane, a, src, rref, f);
         mo = moments(f);
       }
       float inv = 0.0f;
@@ -736,36 +1344,47 @@ __global__ void __launch_bounds__(256) k_export(Params P, Buffers D, int rbuf, f
   }
 }
 
-// Sum of rho_a over the fluid cells of the active blocks, FP64; out[2 + a]
+// Sum of rho_a over the fluid cells of the active blocks, FP64; out[2]
 // counts those cells.
-template <bool PULL>
-__global__ void __launch_bounds__(256) k_mass(Params P, Buffers D, int rbuf, double* out) {
-  const int s = blockIdx.x;
-  if (s >= D.ctrl[kNActive]) return;
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf, double* out) {
+  const int n_active = D.ctrl[kNActive];
+  const int s = slot_of_workgroup(blockIdx.x, n_active);
+  if (s >= n_active) return;
   __shared__ BlockCtx ctx;
-  __shared__ double red[kMaxComp][256];
-  __shared__ int cnt[256];
-  const long long slot_elems = (long long)P.ncomp * kQ * kCells;
-  setup_block(P, D, D.slot_block[s], slot_elems, ctx);
+  __shared__ double red[kMaxComp][kThreads];
+  __shared__ int cnt[kThreads];
+  setup_block(P, D, D.slot_block[s], ctx);
   __syncthreads();
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
+  const uint32_t plane = P.plane;
+  const uint32_t own_base = (uint32_t)s * kCells;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
   double acc[kMaxComp] = {0.0, 0.0};
   int nf = 0;
-  for (int z = 0; z < kB; ++z) {
-    const int c = x + 16 * y + 256 * z;
-    const uint32_t m = D.mask[(long long)s * kCells + c];
+#pragma unroll 1
+  for (int z = z0; z < kB; z += kZStep) {
+    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t m = D.mask[cid];
     if (((m >> kKindShift) & 3u) == kSolid) continue;
     ++nf;
-    for (int a = 0; a < P.ncomp; ++a) {
+    Sources<S::kRef> src;
+    pull_axes_z(z, pa);
+    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
       float f[kQ];
-      load_cell<PULL>(D.f[rbuf], (long long)a * kQ * kCells, x, y, z, m, ctx.nb, f);
+      gather<S>(fb, plane, a, src, rref, f);
       acc[a] += (double)moments(f).rho;
     }
   }
   for (int a = 0; a < kMaxComp; ++a) red[a][threadIdx.x] = acc[a];
   cnt[threadIdx.x] = nf;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       for (int a = 0; a < kMaxComp; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + w];
       cnt[threadIdx.x] += cnt[threadIdx.x + w];
@@ -773,33 +1392,129 @@ __global__ void __launch_bounds__(256) k_mass(Params P, Buffers D, int rbuf, dou
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    for (int a = 0; a < P.ncomp; ++a) atomicAdd(&out[a], red[a][0]);
+    for (int a = 0; a < NC; ++a) atomicAdd(&out[a], red[a][0]);
     atomicAdd(&out[2], (double)cnt[0]);
   }
 }
+
+// Dispatch on storage format and component count.
+template <template <typename, int> class K, typename... A>
+hipError_t dispatch(const Params& P, A&&... args) {
+  if (P.store == 0) {
+    if (P.ncomp == 2) return K<StoreF32, 2>::launch(P, args...);
+    return K<StoreF32, 1>::launch(P, args...);
+  }
+  if (P.ncomp == 2) return K<StoreF16, 2>::launch(P, args...);
+  return K<StoreF16, 1>::launch(P, args...);
+}
+
+template <typename S, int NC>
+struct RestL {
+  static hipError_t launch(const Params& P, const float* bg, float* out, int* it, hipStream_t st) {
+    hipLaunchKernelGGL((k_rest_state<S, NC>), dim3(1), dim3(64), 0, st, P, bg, out, it);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct InitL {
+  static hipError_t launch(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
+                           bool use_init, hipStream_t st) {
+    const int grid = from_dev ? 512 : (count > 0 ? (count < 4096 ? count : 4096) : 1);
+    hipLaunchKernelGGL((k_init<S>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
+                       use_init ? 1 : 0);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct MomentsL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int mode, hipStream_t st) {
+    if (pull)
+      hipLaunchKernelGGL((k_moments<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, mode);
+    else
+      hipLaunchKernelGGL((k_moments<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, mode);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct CollideL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* dp, float* df,
+                           hipStream_t st) {
+    const bool dbg = dp != nullptr;
+    if (pull && !dbg)
+      hipLaunchKernelGGL((k_collide<S, NC, true, 0>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
+    else if (!pull && !dbg)
+      hipLaunchKernelGGL((k_collide<S, NC, false, 0>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
+    else if (pull)
+      hipLaunchKernelGGL((k_collide<S, NC, true, 1>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
+    else
+      hipLaunchKernelGGL((k_collide<S, NC, false, 1>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct FusedL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
+                           hipStream_t st) {
+    const dim3 g(grid_for(P.capacity)), b(kFusedThreads);
+    if (pull && !frontier_pass)
+      hipLaunchKernelGGL((k_fused<S, NC, true, false>), g, b, 0, st, P, D, rbuf);
+    else if (pull)
+      hipLaunchKernelGGL((k_fused<S, NC, true, true>), g, b, 0, st, P, D, rbuf);
+    else if (!frontier_pass)
+      hipLaunchKernelGGL((k_fused<S, NC, false, false>), g, b, 0, st, P, D, rbuf);
+    else
+      hipLaunchKernelGGL((k_fused<S, NC, false, true>), g, b, 0, st, P, D, rbuf);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct CriterionL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int mode, hipStream_t st) {
+    const dim3 g(grid_for(P.capacity)), b(kThreads);
+    if (pull)
+      hipLaunchKernelGGL((k_criterion<S, NC, true>), g, b, 0, st, P, D, rbuf, mode);
+    else
+      hipLaunchKernelGGL((k_criterion<S, NC, false>), g, b, 0, st, P, D, rbuf, mode);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct ExportL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* r, float* u, float* m,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_default, dim3(2048), dim3(256), 0, st, P, D, r, u, m);
+    if (pull)
+      hipLaunchKernelGGL((k_export<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, r, u, m);
+    else
+      hipLaunchKernelGGL((k_export<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, r, u, m);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
+struct MassL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, double* out, hipStream_t st) {
+    if (pull)
+      hipLaunchKernelGGL((k_mass<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, out);
+    else
+      hipLaunchKernelGGL((k_mass<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, out);
+    return hipGetLastError();
+  }
+};
 
 }  // namespace
 
 // --------------------------------------------------------------- launchers
 hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream) {
-  hipLaunchKernelGGL(k_rest_state, dim3(1), dim3(64), 0, stream, P, bg, out, iters);
-  return hipGetLastError();
+  return dispatch<RestL>(P, bg, out, iters, stream);
 }
 
 hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
                              bool use_init, hipStream_t stream) {
-  const int grid = from_dev ? 512 : (count > 0 ? (count < 4096 ? count : 4096) : 1);
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, stream, P, D, buf, first, count, from_dev ? 1 : 0,
-                     use_init ? 1 : 0);
-  return hipGetLastError();
+  return dispatch<InitL>(P, D, buf, first, count, from_dev, use_init, stream);
 }
 
 hipError_t launch_moments(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode, hipStream_t stream) {
-  if (pull)
-    hipLaunchKernelGGL(k_moments<true>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, crit_mode);
-  else
-    hipLaunchKernelGGL(k_moments<false>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, crit_mode);
-  return hipGetLastError();
+  return dispatch<MomentsL>(P, D, rbuf, pull, crit_mode, stream);
 }
 
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream) {
@@ -808,38 +1523,31 @@ hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStrea
 }
 
 hipError_t launch_collide(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream) {
-  if (pull)
-    hipLaunchKernelGGL((k_collide<true, 0>), dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_collide<false, 0>), dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, nullptr, nullptr);
-  return hipGetLastError();
+  return dispatch<CollideL>(P, D, rbuf, pull, (float*)nullptr, (float*)nullptr, stream);
+}
+
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
+                        hipStream_t stream) {
+  return dispatch<FusedL>(P, D, rbuf, pull, frontier_pass, stream);
+}
+
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
+                            hipStream_t stream) {
+  return dispatch<CriterionL>(P, D, rbuf, pull, crit_mode, stream);
 }
 
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u, float* umix,
                          hipStream_t stream) {
-  hipLaunchKernelGGL(k_fill_default, dim3(2048), dim3(256), 0, stream, P, D, rho, u, umix);
-  if (pull)
-    hipLaunchKernelGGL(k_export<true>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, rho, u, umix);
-  else
-    hipLaunchKernelGGL(k_export<false>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, rho, u, umix);
-  return hipGetLastError();
+  return dispatch<ExportL>(P, D, rbuf, pull, rho, u, umix, stream);
 }
 
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out, hipStream_t stream) {
-  if (pull)
-    hipLaunchKernelGGL(k_mass<true>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, out);
-  else
-    hipLaunchKernelGGL(k_mass<false>, dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, out);
-  return hipGetLastError();
+  return dispatch<MassL>(P, D, rbuf, pull, out, stream);
 }
 
 hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi, float* force,
                                hipStream_t stream) {
-  if (pull)
-    hipLaunchKernelGGL((k_collide<true, 1>), dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, psi, force);
-  else
-    hipLaunchKernelGGL((k_collide<false, 1>), dim3(P.capacity), dim3(256), 0, stream, P, D, rbuf, psi, force);
-  return hipGetLastError();
+  return dispatch<CollideL>(P, D, rbuf, pull, psi, force, stream);
 }
 
 }  // namespace lbm
