@@ -110,10 +110,12 @@ typedef struct lbm_stats {
   int32_t pool_full;        /* nonzero if an activation did not fit the pool */
   int64_t activations;      /* blocks activated after t = 0 */
 } lbm_stats_t;
-/* leak: number of (cell, direction) pairs in which an active cell handed a
- * population other than the rest state to a cell of an inactive block, or
- * showed such a cell a pseudo-potential other than the rest one.  It is 0
- * exactly when the progressive mesh reproduces the static mesh. */
+/* leak: number of (step, cell, direction) links in which an active cell
+ * showed a non-solid cell of an inactive block a pseudo-potential other than
+ * the rest one, or handed it a population other than the rest state (same
+ * bits in the stored format) that the block did not take in by activating
+ * at the next step.  It is 0 exactly when the progressive mesh reproduces the
+ * static mesh.  Progressive mode only (0 on a static mesh). */
 
 typedef struct lbm_handle lbm_t;
 
@@ -192,13 +194,12 @@ int lbm_debug_fields(lbm_t* h, int which, double* out);
 /* Per-kernel GPU timing.  lbm_timing_enable(h, 1) records HIP events around
  * every kernel lbm_step launches (on the handle's stream); lbm_timing_read
  * waits for the stream and returns, per kernel k < n (names from
- * lbm_kernel_name: criterion, activate, init_blocks, fused_step,
- * fused_step_frontier), the launch count and total milliseconds, then
- * resets. */
+ * lbm_kernel_name: criterion, activate, init_blocks, fused_step), the launch
+ * count and total milliseconds, then resets. */
 int lbm_timing_enable(lbm_t* h, int enable);
 int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n);
 const char* lbm_kernel_name(int32_t k);
-#define LBM_NUM_KERNELS 5
+#define LBM_NUM_KERNELS 4
 
 /* Releases every resource of the handle (waits for the stream). */
 int lbm_destroy(lbm_t* h);

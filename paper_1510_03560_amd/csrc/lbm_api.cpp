@@ -21,8 +21,7 @@ using namespace lbm;
 namespace {
 
 constexpr int kTraceCap = 1 << 20;
-const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step",
-                                                   "fused_step_frontier"};
+const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step"};
 
 std::string g_create_error;
 
@@ -377,7 +376,6 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.f[1] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
   D.rho[0] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
   D.rho[1] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
-  D.psi = (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane);
   D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * plane);
   D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * plane) : nullptr;
   D.block_slot = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
@@ -385,12 +383,13 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.bfluid = (uint8_t*)dev_alloc(h, P.nb);
   D.solid = (uint8_t*)dev_alloc(h, (size_t)N);
   D.request = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
+  D.expose = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
-  if (!D.f[0] || !D.f[1] || (f16 && (!D.rho[0] || !D.rho[1])) || !D.psi || !D.mask ||
+  if (!D.f[0] || !D.f[1] || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
-      !D.slot_block || !D.bfluid || !D.solid || !D.request || !D.trace)
+      !D.slot_block || !D.bfluid || !D.solid || !D.request || !D.expose || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
-  h->slot_bytes = (int64_t)kCells * ((int64_t)2 * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) + 4 * P.ncomp + 4 +
+  h->slot_bytes = (int64_t)kCells * ((int64_t)2 * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) + 4 +
                                      (h->user.progressive ? 12 * P.ncomp : 0));
   // initial fields, FP32; NaN marks a component of a cell at the rest state
   if (rho0 || u0) {
@@ -421,6 +420,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   HIP_TRY(h, hipMemcpy(D.solid, sol.data(), (size_t)N, hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(D.bfluid, h->bfluid_h.data(), P.nb, hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemsetAsync(D.request, 0, sizeof(int32_t) * P.nb, h->stream));
+  HIP_TRY(h, hipMemsetAsync(D.expose, 0, sizeof(int32_t) * P.nb, h->stream));
   // the rest slot, in both population buffers
   for (int b = 0; b < 2; ++b) {
     hipError_t e = launch_init_slots(P, D, b, P.capacity, 1, false, false, h->stream);
@@ -487,21 +487,19 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     const int rb = h->rbuf;
     int rc;
     if (h->user.progressive) {
-      // criterion on the frontier, then the requested blocks join this step
-      const int mode = h->step == 0 ? 1 : 2;
-      rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, pull, mode, h->stream); });
+      // criterion and leak checks on the frontier, then the requested blocks
+      // join this step
+      const int flags = h->step == 0 ? (kCritRecord | kCritExposure)
+                                     : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
+      rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, pull, flags, h->stream); });
       if (rc) return rc;
       rc = timed(h, 1, [&] { return launch_activate(P, h->D, (int)h->step, h->stream); });
       if (rc) return rc;
       rc = timed(h, 2, [&] { return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream); });
       if (rc) return rc;
     }
-    rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, false, h->stream); });
+    rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
     if (rc) return rc;
-    if (h->user.progressive) {
-      rc = timed(h, 4, [&] { return launch_fused(P, h->D, rb, pull, true, h->stream); });
-      if (rc) return rc;
-    }
     h->rbuf ^= 1;
     h->step++;
   }
@@ -625,18 +623,19 @@ int lbm_debug_fields(lbm_t* h, int which, double* out) {
   const Params& P = h->P;
   const int64_t N = (int64_t)P.nx * P.ny * P.nz;
   const size_t np = (size_t)P.ncomp * N, nf = (size_t)P.ncomp * 3 * N;
+  const size_t ns = (size_t)P.ncomp * P.plane;  // psi per slot
   float* d_p = (float*)dev_alloc(h, sizeof(float) * np);
   float* d_f = (float*)dev_alloc(h, sizeof(float) * nf);
-  if (!d_p || !d_f) {
+  float* d_s = (float*)dev_alloc(h, sizeof(float) * ns);
+  if (!d_p || !d_f || !d_s) {
     if (d_p) dev_free_one(h, d_p, sizeof(float) * np);
     if (d_f) dev_free_one(h, d_f, sizeof(float) * nf);
+    if (d_s) dev_free_one(h, d_s, sizeof(float) * ns);
     return fail(h, LBM_ENOMEM, "device allocation failed (debug)");
   }
   hipError_t e = hipMemsetAsync(d_p, 0, sizeof(float) * np, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d_f, 0, sizeof(float) * nf, h->stream);
-  // psi needs the moments pass of the current state first
-  if (e == hipSuccess) e = launch_moments(P, h->D, h->rbuf, h->step > 0, 0, h->stream);
-  if (e == hipSuccess) e = launch_debug_fields(P, h->D, h->rbuf, h->step > 0, d_p, d_f, h->stream);
+  if (e == hipSuccess) e = launch_debug_fields(P, h->D, h->rbuf, h->step > 0, d_s, d_p, d_f, h->stream);
   std::vector<float> tmp(which == LBM_DEBUG_PSI ? np : nf);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tmp.data(), which == LBM_DEBUG_PSI ? d_p : d_f, sizeof(float) * tmp.size(),
@@ -644,6 +643,7 @@ int lbm_debug_fields(lbm_t* h, int which, double* out) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   dev_free_one(h, d_p, sizeof(float) * np);
   dev_free_one(h, d_f, sizeof(float) * nf);
+  dev_free_one(h, d_s, sizeof(float) * ns);
   if (e != hipSuccess) return fail(h, LBM_EHIP, "debug fields: %s", hipGetErrorString(e));
   for (size_t k = 0; k < tmp.size(); ++k) out[k] = (double)tmp[k];
   return LBM_OK;

@@ -63,7 +63,6 @@ struct Params {
 struct Buffers {
   void* f[2];             // populations: [ncomp*19 planes] of float or __half
   float* rho[2];          // FP16 store only: [ncomp planes] reference densities, double-buffered
-  float* psi;             // [ncomp planes] pseudo-potential of the current step
   uint32_t* mask;         // [1 plane]: bit i = link i bounces; kind in bits 24..25
   float* uprev;           // [ncomp*3 planes] velocity of the previous step (criterion; progressive only)
   int32_t* block_slot;    // [nb] slot of a block, -1 when inactive
@@ -71,6 +70,7 @@ struct Buffers {
   uint8_t* bfluid;        // [nb] block holds a non-solid cell
   uint8_t* solid;         // [nx*ny*nz] solid flags of the whole lattice
   int32_t* request;       // [nb] activation requests
+  int32_t* expose;        // [nb] links that showed a non-rest psi to the block this step
   int32_t* ctrl;          // [kNumCtrl]
   unsigned long long* counters;  // [0] leak, [1] clamps
   int32_t* trace;         // [trace_cap][2] (step, block)
@@ -86,22 +86,25 @@ struct Buffers {
 hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream);
 hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first_slot_host, int count_host,
                              bool from_device_counts, bool use_initial_fields, hipStream_t stream);
-hipError_t launch_moments(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
-                          hipStream_t stream);
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream);
-hipError_t launch_collide(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
-// Fused step kernel (moments, psi, forces, collision, streaming); the
-// frontier pass runs the blocks next to inactive blocks with the leak check.
-hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
-                        hipStream_t stream);
-// Criterion of Eq 13 on the shell cells of frontier blocks.
-hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
+// Fused step kernel: moments, psi, forces, collision and streaming.
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
+// Criterion of Eq 13 and leak checks on the shell cells of frontier blocks.
+enum : int {
+  kCritRecord = 1,    // store this step's velocities for the next comparison
+  kCritEval = 2,      // compare with the stored velocities, request blocks
+  kCritExposure = 4,  // check the psi shown to inactive blocks
+  kCritEmission = 8,  // check the populations the last step handed to inactive blocks
+};
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
                             hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
                          float* umix, hipStream_t stream);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,
                        hipStream_t stream);
-hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi,
-                               float* force, hipStream_t stream);
+// Test dump: psi_slots = device scratch of ncomp planes; psi (ncomp*N) and
+// force (ncomp*3*N) lattice-wide device outputs.
+hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots,
+                               float* psi, float* force, hipStream_t stream);
 
 }  // namespace lbm

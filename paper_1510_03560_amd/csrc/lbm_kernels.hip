@@ -14,16 +14,18 @@
 // every inactive block and for the outside of the domain.
 //
 // One time step (section 4.3) runs
-//   k_moments  : pull f(t) -> rho, u; psi (Eq 4-7); criterion of Eq 13 on the
-//                boundary shell of frontier blocks -> activation requests
-//   k_activate : compact requests into new slots (wave ballot + scan)
-//   k_init     : new slots take the rest state
-//   k_collide  : psi halo staged in LDS -> forces (Eq 8-9); BGK collision with
-//                exact-difference forcing (Eq 10-12); pull streaming with
-//                half-way bounce-back; aligned store of f*(t)
-// The state between steps is the post-collision f*; the first step of a run
-// reads the initial populations in place instead of pulling.
-//
+//   k_criterion : frontier blocks only: pull the shell cells, Eq 13 ->
+//                 activation requests; leak checks
+//   k_activate  : compact requests into new slots (wave ballot + scan)
+//   k_init      : new slots take the rest state
+//   k_fused     : per active block, a z-sweep that pulls f(t) with half-way
+//                 bounce-back, takes rho, psi (Eq 4-7) into LDS, the forces
+//                 (Eq 8-9) from the LDS psi stencil, BGK collision with
+//                 exact-difference forcing (Eq 10-12), and stores f*(t)
+// (a static mesh runs k_fused only).  The state between steps is the
+// post-collision f*; the first step of a run reads the initial populations
+// in place instead of pulling.
+
 // Storage formats: FP32, or FP16 deviations h = s (f - w_i rho_ref) with
 // rho_ref the writing cell's own density of that step (kept, double-buffered,
 // in `rho`), s = 2^12; arithmetic is FP32 in both.
@@ -31,7 +33,7 @@
 // Every floating-point expression is written out explicitly and the library
 // is compiled without floating-point contraction, so the same inputs give the
 // same bits in every kernel.  That makes the rest state computed by
-// k_rest_state an exact fixed point of k_moments + k_collide, which is what
+// k_rest_state an exact fixed point of k_fused, which is what
 // lets a progressive run reproduce the static run bit for bit.
 
 #include <hip/hip_fp16.h>
@@ -472,8 +474,7 @@ __device__ __forceinline__ typename S::T rest_stored(const Params& P, int a, int
 // Iterates the update of a cell whose every neighbour is itself (uniform
 // lattice at rest, density bg) until the stored populations (and, for the
 // FP16 store, the reference density) stop changing; the same device
-// functions as k_moments/k_collide, so the result is a fixed point of the
-// real update.  Single thread; tiny.
+// functions as k_fused, so the result is a fixed point of the real update.  Single thread; tiny.
 //   out: [2*19] stored bits, then decoded populations [2*19], then
 //   reference density [2], density [2], psi [2] (as floats).
 template <typename S, int NC>
@@ -604,7 +605,6 @@ __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int 
         const float rref = at_rest ? P.rho_ref_rest[a] : moments(fe).rho;
         for (int i = 0; i < kQ; ++i)
           fb[(size_t)(a * kQ + i) * plane + cid] = at_rest ? rest_stored<S>(P, a, i) : S::encode(fe[i], dir_w(i) * rref);
-        D.psi[(size_t)a * plane + cid] = P.psi_rest[a];
         if constexpr (S::kRef) {
           D.rho[0][(size_t)a * plane + cid] = rref;
           D.rho[1][(size_t)a * plane + cid] = rref;
@@ -616,92 +616,47 @@ __global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int 
   }
 }
 
-// --------------------------------------------------------------- moments
-// K1: per active block, pull f(t), compute rho_a, u_a (Eq 4-5) and psi_a
-// (Eq 6-7) for every cell; store psi (and, for the FP16 store, rho as the
-// next reference).  On frontier blocks (an inactive neighbour holding fluid),
-// evaluate Eq 13: a fluid cell within `shell` cells of such a neighbour whose
-// velocity differs from the previous step's, for any component, requests
-// that neighbour (section 4.2).  crit_mode: 0 = no criterion, 1 = only record
-// velocities (first step), 2 = evaluate and record.
+// ------------------------------------------------------------ debug psi
+// Test dump, first pass: psi (Eq 6-7) of every non-solid cell of the active
+// blocks into a slot-indexed buffer, exactly as the step computes it (pulled
+// densities; inlet nodes psi(inlet density), outlet nodes the rest value).
 template <typename S, int NC, bool PULL>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_moments(Params P, Buffers D, int rbuf, int crit_mode) {
+__global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int rbuf, float* psi_out) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
   if (s >= n_active) return;
   __shared__ BlockCtx ctx;
   setup_block(P, D, D.slot_block[s], ctx);
   __syncthreads();
-  const unsigned cand = crit_mode ? ctx.cand : 0u;
   const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
-  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // densities of the previous step
-  float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
   const uint32_t own_base = (uint32_t)s * kCells;
-  unsigned fired = 0u;
-  unsigned numeric = 0u, clamps = 0u;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
     const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
     const uint32_t m = ld(D.mask, cid * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
-    // solid cells have no populations to pull; their psi is never read (a
-    // solid neighbour contributes the centre's own psi)
     if (kind == kSolid) continue;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
     sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
-    float f[NC][kQ];
-#pragma unroll
-    for (int a = 0; a < NC; ++a) gather<S>(fb, plane, a, src, rref, f[a]);
-    const unsigned dirs = cand ? (shell_dirs(x, y, z, P.shell) & cand) : 0u;
-    bool changed = false;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-      const Mom mo = moments(f[a]);
-      float psi = 0.0f;
+      float f[kQ];
+      gather<S>(fb, plane, a, src, rref, f);
+      float psi = P.psi_rest[a];
       if (kind == kFluid) {
         bool cl;
-        psi = pseudo_potential(P, a, mo.rho, cl);
-        clamps += cl ? 1u : 0u;
-        if (!(mo.rho > 0.0f && mo.rho < 3.0e38f)) numeric = 1u;
+        psi = pseudo_potential(P, a, moments(f).rho, cl);
       } else if (kind == kInlet) {
         psi = P.psi_in[a];
-      } else if (kind == kOutlet) {
-        psi = P.psi_rest[a];
       }
-      st(D.psi + (size_t)a * plane, cid * 4u, psi);
-      if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, mo.rho);
-      if (dirs && kind != kSolid) {
-        float inv = 0.0f;
-        if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
-        const float u[3] = {mo.jx * inv, mo.jy * inv, mo.jz * inv};
-        float* up = D.uprev + (size_t)(a * 3) * plane + cid;
-        if (crit_mode == 2) {
-          float d2 = 0.0f;
-          bool diff = false;
-          for (int d = 0; d < 3; ++d) {
-            const float dd = u[d] - up[(size_t)d * plane];
-            diff = diff || (dd != 0.0f);
-            d2 = d2 + dd * dd;
-          }
-          changed = changed || (P.s_zero ? diff : (sqrtf(d2) > P.S));
-        }
-        for (int d = 0; d < 3; ++d) up[(size_t)d * plane] = u[d];
-      }
+      st(psi_out + (size_t)a * plane, cid * 4u, psi);
     }
-    if (changed) fired |= dirs;
-  }
-  if (numeric) atomicOr(&D.ctrl[kNumeric], 1);
-  if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
-  if (cand) {
-    if (fired) atomicOr(&ctx.fired, fired);
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t < 27 && ((ctx.fired >> t) & 1u)) D.request[ctx.nbk[t]] = 1;
   }
 }
 
@@ -753,6 +708,17 @@ __global__ void __launch_bounds__(1024) k_activate(Params P, Buffers D, int step
     base += chunk_total;
     __syncthreads();
   }
+  // failing links recorded by the criterion: leaks if their block is still
+  // inactive now that this step's activations are done
+  unsigned long long leak = 0ull;
+  for (int b = t; b < P.nb; b += 1024) {
+    const int e = D.expose[b];
+    if (e) {
+      if (D.block_slot[b] < 0) leak += (unsigned long long)e;
+      D.expose[b] = 0;
+    }
+  }
+  if (leak) atomicAdd(&D.counters[0], leak);
   if (t == 0) {
     D.ctrl[kNewFirst] = n0;
     D.ctrl[kNewCount] = base - n0;
@@ -762,86 +728,60 @@ __global__ void __launch_bounds__(1024) k_activate(Params P, Buffers D, int step
   }
 }
 
-// --------------------------------------------------------------- collide
-// K2: per active block, stage psi of the 18^3 halo (block plus one cell) for
-// every component in LDS, then per cell: pull f(t), moments, forces from the
-// LDS psi stencil (Eq 8-9), collision with exact-difference forcing
-// (Eq 10-12), boundary nodes impose their state, aligned store of f*(t) to
-// the other buffer.  MODE 1 instead writes psi and the force to lattice-wide
-// debug arrays.  Frontier blocks also count leaks: a non-rest population or
-// potential handed to a cell of an inactive block.
+// ----------------------------------------------------------- debug force
+// Test dump, second pass: psi and the total force (Eq 8-9 plus body force)
+// of every non-solid cell of the active blocks, written to lattice-wide
+// arrays.  Psi of the 18^3 halo is staged in LDS from the first pass;
+// inactive and outside blocks show the rest value.
 constexpr int kH = kB + 2;            // halo edge
 constexpr int kHalo = kH * kH * kH;   // 5832 cells
 
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x + 1) + kH * ((y + 1) + kH * (z + 1)); }
 
-template <typename S, int NC, bool PULL, int MODE>
-__global__ void __launch_bounds__(kThreads) k_collide(Params P, Buffers D, int rbuf, float* dbg_psi,
-                                                       float* dbg_force) {
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, int rbuf, const float* psi_slots,
+                                                          float* dbg_psi, float* dbg_force) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
   if (s >= n_active) return;
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[NC * kHalo];
-  __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
-  __shared__ uint32_t f_rest_bits_s[NC][kQ];
   const int blk = D.slot_block[s];
   setup_block(P, D, blk, ctx);
-  if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
-    const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
-    f_in_s[a][i] = P.f_in[a][i];
-    f_rest_s[a][i] = P.f_rest[a][i];
-    f_rest_bits_s[a][i] = P.f_rest_bits[a][i];
-  }
   __syncthreads();
   const uint32_t plane = P.plane;
   for (int h = threadIdx.x; h < kHalo; h += blockDim.x) {
     const int hx = h % kH - 1, hy = (h / kH) % kH - 1, hz = h / (kH * kH) - 1;
     const int d = 13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(hz);
-    const uint32_t cid = (uint32_t)ctx.nslot[d] * kCells + (uint32_t)((hx & 15) + 16 * (hy & 15) + 256 * (hz & 15));
+    const int slot = ctx.nslot[d];
+    const uint32_t cid = (uint32_t)slot * kCells + (uint32_t)((hx & 15) + 16 * (hy & 15) + 256 * (hz & 15));
 #pragma unroll
-    for (int a = 0; a < NC; ++a) psi_s[a * kHalo + h] = ld(D.psi + (size_t)a * plane, cid * 4u);
+    for (int a = 0; a < NC; ++a)
+      psi_s[a * kHalo + h] = slot == P.capacity ? P.psi_rest[a] : ld(psi_slots + (size_t)a * plane, cid * 4u);
   }
   __syncthreads();
   const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
-  typename S::T* __restrict__ fw = fplane<S>(D, rbuf ^ 1);
-  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;      // references of f(t)
-  const float* __restrict__ rcur = S::kRef ? D.rho[rbuf ^ 1] : nullptr;  // this step's densities
-  const bool frontier = ctx.cand != 0u;
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
   const uint32_t own_base = (uint32_t)s * kCells;
-  // Stores value v of population (a, i) of cell cid in the storage format.
-  auto emit = [&](uint32_t cid, int a, auto I, float v, float rr) {
-    constexpr int i = decltype(I)::value;
-    // plane i addressed from the first plane of its opposite pair
-    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-    constexpr bool second = i != 0 && !(i & 1);
-    const uint32_t off = (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T);
-    st(fw + (size_t)(a * kQ + first) * plane, off, S::encode(v, dir_w(i) * rr));
-  };
-  // reference density of the FP16 store: this cell's density of this step
-  auto ref_of = [&](uint32_t cid, int a) -> float {
-    if constexpr (S::kRef) return ld(rcur + (size_t)a * plane, cid * 4u);
-    return 0.0f;
-  };
-  if constexpr (MODE == 0) {
-    // fluid cells: pull, forces, collision, store
+  const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
+  const long long N = (long long)P.nx * P.ny * P.nz;
 #pragma unroll 1
-    for (int z = z0; z < kB; z += kZStep) {
-      const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
-      const uint32_t m = ld(D.mask, cid * 4u);
-      if (((m >> kKindShift) & 3u) != kFluid) continue;
-      const int h0 = hidx(x, y, z);
-      float psi_c[NC];
+  for (int z = z0; z < kB; z += kZStep) {
+    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t m = ld(D.mask, cid * 4u);
+    const uint32_t kind = (m >> kKindShift) & 3u;
+    if (kind == kSolid) continue;
+    const int h0 = hidx(x, y, z);
+    float psi_c[NC];
 #pragma unroll
-      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[a * kHalo + h0];
-      Sources<S::kRef> src;
-      pull_axes_z(z, pa);
-      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
-      // forces of every component first: they need only psi
-      Vec3 F[NC];
+    for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[a * kHalo + h0];
+    Vec3 F[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) F[a] = Vec3{0.0f, 0.0f, 0.0f};
+    if (kind == kFluid)
       interaction_forces<NC>(P, psi_c,
                              [&](int a, int i) {
                                const int hn = h0 + dir_ex(i) + kH * (dir_ey(i) + kH * dir_ez(i));
@@ -849,113 +789,19 @@ __global__ void __launch_bounds__(kThreads) k_collide(Params P, Buffers D, int r
                                return solid_nb ? psi_c[a] : psi_s[a * kHalo + hn];
                              },
                              F);
-      // then one component at a time: pull, collide, store (the barrier keeps
-      // the next component's loads below these stores)
+    Sources<S::kRef> src;
+    pull_axes_z(z, pa);
+    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        if (a > 0) __builtin_amdgcn_sched_barrier(0);
-        float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
-        const Mom mo = moments(f);
-        const float rr = ref_of(cid, a);
-        collide_emit(P.omega[a], f, mo, add_body(P, a, F[a], mo.rho),
-                     [&](auto I, float v) { emit(cid, a, I, v, rr); });
-      }
-    }
-    // boundary nodes impose their state (only blocks on an inlet/outlet face)
-    if (ctx.has_bc) {
-#pragma unroll 1
-      for (int z = z0; z < kB; z += kZStep) {
-        const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
-        const uint32_t kind = (ld(D.mask, cid * 4u) >> kKindShift) & 3u;
-        if (kind != kInlet && kind != kOutlet) continue;
-        for (int a = 0; a < NC; ++a) {
-          const float rr = ref_of(cid, a);
-          unroll<kQ>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            emit(cid, a, I, kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], rr);
-          });
-        }
-      }
-    }
-    // Leak check (blocks next to an inactive block): what each cell handed
-    // to a cell of an inactive block must be the rest state, in the stored
-    // format a reader would see.  Reads back this thread's own stores.
-    if (frontier) {
-      unsigned long long leak = 0ull;
-#pragma unroll 1
-      for (int z = z0; z < kB; z += kZStep) {
-        const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
-        const uint32_t m = ld(D.mask, cid * 4u);
-        if (((m >> kKindShift) & 3u) == kSolid) continue;
-        if (x > 0 && x < 15 && y > 0 && y < 15 && z > 0 && z < 15) continue;
-        const int h0 = hidx(x, y, z);
-        bool bad_cell = false;
-        for (int a = 0; a < NC; ++a) {
-          bad_cell = bad_cell || (psi_s[a * kHalo + h0] != P.psi_rest[a]);
-          if constexpr (S::kRef) bad_cell = bad_cell || (ref_of(cid, a) != P.rho_ref_rest[a]);
-        }
-        uint32_t bad_dirs = 0u;
-        unroll<kQ - 1>([&](auto I) {
-          constexpr int i = decltype(I)::value + 1;
-          constexpr int first = (i & 1) ? i : i - 1;
-          constexpr bool second = !(i & 1);
-          const int tx = x + dir_ex(i), ty = y + dir_ey(i), tz = z + dir_ez(i);
-          const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
-          const bool outside_or_solid = (m >> dir_opp(i)) & 1u;
-          if (d != 13 && ctx.nslot[d] == P.capacity && !outside_or_solid) {
-            bool differs = bad_cell;
-            for (int a = 0; a < NC; ++a) {
-              const uint32_t off = (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T);
-              const typename S::T v = ld(fw + (size_t)(a * kQ + first) * plane, off);
-              differs = differs || (S::bits(v) != f_rest_bits_s[a][i]);
-            }
-            if (differs) bad_dirs |= 1u << i;
-          }
-        });
-        leak += (unsigned long long)__popc(bad_dirs);
-      }
-      if (leak) atomicAdd(&D.counters[0], leak);
-    }
-  } else {
-    // debug: psi and the total force of every fluid cell
-    const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
-    const long long N = (long long)P.nx * P.ny * P.nz;
-#pragma unroll 1
-    for (int z = z0; z < kB; z += kZStep) {
-      const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
-      const uint32_t m = ld(D.mask, cid * 4u);
-      const uint32_t kind = (m >> kKindShift) & 3u;
-      if (kind == kSolid) continue;
-      const int h0 = hidx(x, y, z);
-      float psi_c[NC];
-#pragma unroll
-      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[a * kHalo + h0];
-      Vec3 F[NC];
-#pragma unroll
-      for (int a = 0; a < NC; ++a) F[a] = Vec3{0.0f, 0.0f, 0.0f};
-      if (kind == kFluid)
-        interaction_forces<NC>(P, psi_c,
-                               [&](int a, int i) {
-                                 const int hn = h0 + dir_ex(i) + kH * (dir_ey(i) + kH * dir_ez(i));
-                                 const bool solid_nb = (m >> dir_opp(i)) & 1u;
-                                 return solid_nb ? psi_c[a] : psi_s[a * kHalo + hn];
-                               },
-                               F);
-      Sources<S::kRef> src;
-      pull_axes_z(z, pa);
-      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
-      const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
-        const Vec3 Fa = kind == kFluid ? add_body(P, a, F[a], moments(f).rho) : F[a];
-        dbg_psi[a * N + n] = psi_c[a];
-        dbg_force[(a * 3 + 0) * N + n] = Fa.x;
-        dbg_force[(a * 3 + 1) * N + n] = Fa.y;
-        dbg_force[(a * 3 + 2) * N + n] = Fa.z;
-      }
+    for (int a = 0; a < NC; ++a) {
+      float f[kQ];
+      gather<S>(fb, plane, a, src, rref, f);
+      const Vec3 Fa = kind == kFluid ? add_body(P, a, F[a], moments(f).rho) : F[a];
+      dbg_psi[a * N + n] = psi_c[a];
+      dbg_force[(a * 3 + 0) * N + n] = Fa.x;
+      dbg_force[(a * 3 + 1) * N + n] = Fa.y;
+      dbg_force[(a * 3 + 2) * N + n] = Fa.z;
     }
   }
 }
@@ -976,13 +822,12 @@ __global__ void __launch_bounds__(kThreads) k_collide(Params P, Buffers D, int r
 // memory; the populations are read once (plus the ring and the two halo
 // planes, which neighbouring blocks also read) and written once.
 // Boundary nodes impose their state in a post-pass (blocks on an inlet or
-// outlet face only).  LEAK instantiations run on frontier blocks only (the
-// others exit) and count what a cell hands to a cell of an inactive block.
+// outlet face only).
 constexpr int kFusedThreads = 384;
 constexpr int kPsiRing = 4;
 constexpr int kFoot = kH * kH;  // 324 columns
 
-template <typename S, int NC, bool PULL, bool LEAK>
+template <typename S, int NC, bool PULL>
 __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, int rbuf) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
@@ -990,16 +835,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
   __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
-  __shared__ uint32_t f_rest_bits_s[NC][kQ];
   setup_block(P, D, D.slot_block[s], ctx);
   if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
     const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
     f_in_s[a][i] = P.f_in[a][i];
     f_rest_s[a][i] = P.f_rest[a][i];
-    f_rest_bits_s[a][i] = P.f_rest_bits[a][i];
   }
   __syncthreads();
-  if ((ctx.cand != 0u) != LEAK) return;  // uniform: frontier blocks run the LEAK variant
   const int t = threadIdx.x;
   const bool col = t < kFoot;
   const bool interior = t < 256;
@@ -1039,7 +881,6 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
   uint32_t mp = 0u;   // and its mask
   bool collide_next = false;
   unsigned numeric = 0u, clamps = 0u;
-  unsigned long long leak = 0ull;
 #pragma unroll 1
   for (int k = 0; k < kH; ++k) {
     const int z = k - 1;
@@ -1099,35 +940,19 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
                                return solid_nb ? psi_c[a] : psi_s[sl[1 + dir_ez(i)]][a][hn];
                              },
                              F);
-      bool bad_psi = false;
-      if constexpr (LEAK) {
-#pragma unroll
-        for (int a = 0; a < NC; ++a) bad_psi = bad_psi || (psi_c[a] != P.psi_rest[a]);
-      }
-      uint32_t bad_dirs = 0u;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         Mom mo = moments(fp[a]);
         const float rr = rp[a];  // FP16 reference: this cell's density of this step
         if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
-        const bool bad_ref = S::kRef && (rr != P.rho_ref_rest[a]);
         collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho), [&](auto I, float v) {
           constexpr int i = decltype(I)::value;
           constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
           constexpr bool second = i != 0 && !(i & 1);
           const typename S::T enc = S::encode(v, dir_w(i) * rr);
           st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-          if constexpr (LEAK && i > 0) {
-            const int tx = cx + dir_ex(i), ty = cy + dir_ey(i), tz = zc + dir_ez(i);
-            const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
-            const bool outside_or_solid = (mp >> dir_opp(i)) & 1u;
-            const bool inactive = d != 13 && ctx.nslot[d] == P.capacity;
-            const bool differs = S::bits(enc) != f_rest_bits_s[a][i] || bad_ref || bad_psi;
-            if (!outside_or_solid && inactive && differs) bad_dirs |= 1u << i;
-          }
         });
       }
-      if constexpr (LEAK) leak += (unsigned long long)__popc(bad_dirs);
     }
     // ---- keep plane z for its collision at the next iteration
     collide_next = interior && fluid && z >= 0 && z < kB;
@@ -1166,15 +991,6 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
           st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
         }
       }
-      bool bad_cell = false;
-      if constexpr (LEAK) {
-#pragma unroll
-        for (int a = 0; a < NC; ++a) {
-          bad_cell = bad_cell || (kind == kInlet ? P.psi_in[a] : P.psi_rest[a]) != P.psi_rest[a];
-          if constexpr (S::kRef) bad_cell = bad_cell || (rr[a] != P.rho_ref_rest[a]);
-        }
-      }
-      uint32_t bad_dirs = 0u;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         unroll<kQ>([&](auto I) {
@@ -1183,88 +999,163 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
           constexpr bool second = i != 0 && !(i & 1);
           const typename S::T enc = S::encode(kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], dir_w(i) * rr[a]);
           st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-          if constexpr (LEAK && i > 0) {
-            const int tx = cx + dir_ex(i), ty = cy + dir_ey(i), tz = z + dir_ez(i);
-            const int d = 13 + sgn_out(tx) + 3 * sgn_out(ty) + 9 * sgn_out(tz);
-            const bool outside_or_solid = (m >> dir_opp(i)) & 1u;
-            const bool inactive = d != 13 && ctx.nslot[d] == P.capacity;
-            if (!outside_or_solid && inactive && (S::bits(enc) != f_rest_bits_s[a][i] || bad_cell))
-              bad_dirs |= 1u << i;
-          }
         });
       }
-      if constexpr (LEAK) leak += (unsigned long long)__popc(bad_dirs);
     }
   }
   if (numeric) atomicOr(&D.ctrl[kNumeric], 1);
   if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
-  if constexpr (LEAK) {
-    if (leak) atomicAdd(&D.counters[0], leak);
-  }
 }
 
 // ------------------------------------------------------------- criterion
 // Eq 13 on frontier blocks only (section 4.2): a fluid cell within `shell`
 // cells of an inactive neighbour block that holds fluid, whose velocity
 // differs from the previous step's for any component, requests that block.
-// Only the shell cells of frontier blocks are pulled, so once the mesh covers
-// the domain this kernel does no work.  crit_mode 1 only records velocities.
+// Only the shell cells of frontier blocks are read, so once the mesh covers
+// the domain this kernel does no work.
+//
+// The same pass checks that the progressive mesh hides nothing (the leak
+// counter).  For a link from an active cell x into a non-solid cell of an
+// inactive block N:
+//  - kCritEmission: the populations the previous step stored at x for the
+//    link (and, for the FP16 store, their reference density) must have the
+//    rest state's bits if N is still inactive now: N's cells would have
+//    pulled them this step;
+//  - kCritExposure: psi(x) of this step must be the rest value if N is still
+//    inactive when this step's forces are taken.
+// Both depend on this step's activation, so the failing links are counted
+// per target block in D.expose and settled by k_activate.
+// The shell cells of a block are first compacted into an LDS list (in any
+// order: every result is a per-cell store, an integer atomic or a bit OR), so
+// that all threads work on them together.
 template <typename S, int NC, bool PULL>
-__global__ void __launch_bounds__(kThreads) k_criterion(Params P, Buffers D, int rbuf, int crit_mode) {
+__global__ void __launch_bounds__(kThreads) k_criterion(Params P, Buffers D, int rbuf, int flags) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
   if (s >= n_active) return;
   __shared__ BlockCtx ctx;
+  __shared__ int expo[27];
+  __shared__ uint16_t list[kCells];
+  __shared__ int count;
   setup_block(P, D, D.slot_block[s], ctx);
+  if (threadIdx.x < 27) expo[threadIdx.x] = 0;
+  if (threadIdx.x == 0) count = 0;
   __syncthreads();
   const unsigned cand = ctx.cand;
   if (!cand) return;  // uniform
-  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
-  PullAxes pa;
-  pull_axes_xy(x, y, pa);
+  for (int c = threadIdx.x; c < kCells; c += kThreads) {
+    const bool in_shell = (shell_dirs(c & 15, (c >> 4) & 15, c >> 8, P.shell) & cand) != 0u;
+    const unsigned long long bal = __ballot(in_shell);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&count, __popcll(bal));
+    base = __shfl(base, 0);
+    if (in_shell) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)c;
+  }
+  __syncthreads();
+  const int n_shell = count;
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
   const uint32_t own_base = (uint32_t)s * kCells;
+  const bool pull_cells = (flags & (kCritRecord | kCritEval | kCritExposure)) != 0;
   unsigned fired = 0u;
 #pragma unroll 1
-  for (int z = z0; z < kB; z += kZStep) {
+  for (int j = threadIdx.x; j < n_shell; j += kThreads) {
+    const int c = list[j];
+    const int x = c & 15, y = (c >> 4) & 15, z = c >> 8;
     const unsigned dirs = shell_dirs(x, y, z, P.shell) & cand;
-    if (!dirs) continue;
-    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t cid = own_base + (uint32_t)c;
     const uint32_t m = ld(D.mask, cid * 4u);
-    if (((m >> kKindShift) & 3u) == kSolid) continue;
-    Sources<S::kRef> src;
-    pull_axes_z(z, pa);
-    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
-    bool changed = false;
+    const uint32_t kind = (m >> kKindShift) & 3u;
+    if (kind == kSolid) continue;
+    // links x -> x + e_i into a non-solid cell of a candidate block
+    uint32_t out_links = 0u;
+    unroll<kQ - 1>([&](auto I) {
+      constexpr int i = decltype(I)::value + 1;
+      const int d = 13 + sgn_out(x + dir_ex(i)) + 3 * sgn_out(y + dir_ey(i)) + 9 * sgn_out(z + dir_ez(i));
+      const bool target_solid = (m >> dir_opp(i)) & 1u;  // x + e_i solid or outside
+      if (d != 13 && ((cand >> d) & 1u) && !target_solid) out_links |= 1u << i;
+    });
+    uint32_t bad = 0u;  // failing links
+    if ((flags & kCritEmission) && out_links) {
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      float f[kQ];
-      gather<S>(fb, plane, a, src, rref, f);
-      const Mom mo = moments(f);
-      float inv = 0.0f;
-      if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
-      const float u[3] = {mo.jx * inv, mo.jy * inv, mo.jz * inv};
-      float* up = D.uprev + (size_t)(a * 3) * plane + cid;
-      if (crit_mode == 2) {
-        float d2 = 0.0f;
-        bool diff = false;
-        for (int d = 0; d < 3; ++d) {
-          const float dd = u[d] - up[(size_t)d * plane];
-          diff = diff || (dd != 0.0f);
-          d2 = d2 + dd * dd;
+      for (int a = 0; a < NC; ++a) {
+        unroll<kQ - 1>([&](auto I) {
+          constexpr int i = decltype(I)::value + 1;
+          constexpr int first = (i & 1) ? i : i - 1;
+          constexpr bool second = !(i & 1);
+          if ((out_links >> i) & 1u) {
+            const typename S::T v = ld(fb + (size_t)(a * kQ + first) * plane,
+                                       (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T));
+            if (S::bits(v) != P.f_rest_bits[a][i]) bad |= 1u << i;
+          }
+        });
+        if constexpr (S::kRef) {
+          if (__float_as_uint(ld(rref + (size_t)a * plane, cid * 4u)) != __float_as_uint(P.rho_ref_rest[a]))
+            bad = out_links;
         }
-        changed = changed || (P.s_zero ? diff : (sqrtf(d2) > P.S));
       }
-      for (int d = 0; d < 3; ++d) up[(size_t)d * plane] = u[d];
     }
-    if (changed) fired |= dirs;
+    if (pull_cells) {
+      PullAxes pa;
+      pull_axes_xy(x, y, pa);
+      pull_axes_z(z, pa);
+      Sources<S::kRef> src;
+      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+      bool changed = false, psi_differs = false;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        float f[kQ];
+        gather<S>(fb, plane, a, src, rref, f);
+        const Mom mo = moments(f);
+        float psi = P.psi_rest[a];
+        if (kind == kFluid) {
+          bool cl;
+          psi = pseudo_potential(P, a, mo.rho, cl);
+        } else if (kind == kInlet) {
+          psi = P.psi_in[a];
+        }
+        psi_differs = psi_differs || (psi != P.psi_rest[a]);
+        if (flags & (kCritRecord | kCritEval)) {
+          float inv = 0.0f;
+          if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
+          const float u[3] = {mo.jx * inv, mo.jy * inv, mo.jz * inv};
+          float* up = D.uprev + (size_t)(a * 3) * plane + cid;
+          if (flags & kCritEval) {
+            float d2 = 0.0f;
+            bool diff = false;
+            for (int d = 0; d < 3; ++d) {
+              const float dd = u[d] - up[(size_t)d * plane];
+              diff = diff || (dd != 0.0f);
+              d2 = d2 + dd * dd;
+            }
+            changed = changed || (P.s_zero ? diff : (sqrtf(d2) > P.S));
+          }
+          if (flags & kCritRecord)
+            for (int d = 0; d < 3; ++d) up[(size_t)d * plane] = u[d];
+        }
+      }
+      if (changed) fired |= dirs;
+      if ((flags & kCritExposure) && psi_differs) bad = out_links;
+    }
+    if (bad) {
+      unroll<kQ - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        if ((bad >> i) & 1u) {
+          const int d = 13 + sgn_out(x + dir_ex(i)) + 3 * sgn_out(y + dir_ey(i)) + 9 * sgn_out(z + dir_ez(i));
+          atomicAdd(&expo[d], 1);
+        }
+      });
+    }
   }
   if (fired) atomicOr(&ctx.fired, fired);
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < 27 && ((ctx.fired >> t) & 1u)) D.request[ctx.nbk[t]] = 1;
+  if (t < 27) {
+    if ((ctx.fired >> t) & 1u) D.request[ctx.nbk[t]] = 1;
+    if (expo[t]) atomicAdd(&D.expose[ctx.nbk[t]], expo[t]);
+  }
 }
 
 // ---------------------------------------------------------------- export
@@ -1426,55 +1317,39 @@ struct InitL {
   }
 };
 template <typename S, int NC>
-struct MomentsL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int mode, hipStream_t st) {
-    if (pull)
-      hipLaunchKernelGGL((k_moments<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, mode);
-    else
-      hipLaunchKernelGGL((k_moments<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, mode);
-    return hipGetLastError();
-  }
-};
-template <typename S, int NC>
-struct CollideL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* dp, float* df,
-                           hipStream_t st) {
-    const bool dbg = dp != nullptr;
-    if (pull && !dbg)
-      hipLaunchKernelGGL((k_collide<S, NC, true, 0>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
-    else if (!pull && !dbg)
-      hipLaunchKernelGGL((k_collide<S, NC, false, 0>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
-    else if (pull)
-      hipLaunchKernelGGL((k_collide<S, NC, true, 1>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
-    else
-      hipLaunchKernelGGL((k_collide<S, NC, false, 1>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, dp, df);
+struct DebugL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots, float* dp,
+                           float* df, hipStream_t st) {
+    const dim3 g(grid_for(P.capacity)), b(kThreads);
+    if (pull) {
+      hipLaunchKernelGGL((k_debug_psi<S, NC, true>), g, b, 0, st, P, D, rbuf, psi_slots);
+      hipLaunchKernelGGL((k_debug_force<S, NC, true>), g, b, 0, st, P, D, rbuf, psi_slots, dp, df);
+    } else {
+      hipLaunchKernelGGL((k_debug_psi<S, NC, false>), g, b, 0, st, P, D, rbuf, psi_slots);
+      hipLaunchKernelGGL((k_debug_force<S, NC, false>), g, b, 0, st, P, D, rbuf, psi_slots, dp, df);
+    }
     return hipGetLastError();
   }
 };
 template <typename S, int NC>
 struct FusedL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
-                           hipStream_t st) {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kFusedThreads);
-    if (pull && !frontier_pass)
-      hipLaunchKernelGGL((k_fused<S, NC, true, false>), g, b, 0, st, P, D, rbuf);
-    else if (pull)
-      hipLaunchKernelGGL((k_fused<S, NC, true, true>), g, b, 0, st, P, D, rbuf);
-    else if (!frontier_pass)
-      hipLaunchKernelGGL((k_fused<S, NC, false, false>), g, b, 0, st, P, D, rbuf);
+    if (pull)
+      hipLaunchKernelGGL((k_fused<S, NC, true>), g, b, 0, st, P, D, rbuf);
     else
-      hipLaunchKernelGGL((k_fused<S, NC, false, true>), g, b, 0, st, P, D, rbuf);
+      hipLaunchKernelGGL((k_fused<S, NC, false>), g, b, 0, st, P, D, rbuf);
     return hipGetLastError();
   }
 };
 template <typename S, int NC>
 struct CriterionL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int mode, hipStream_t st) {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int flags, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kThreads);
     if (pull)
-      hipLaunchKernelGGL((k_criterion<S, NC, true>), g, b, 0, st, P, D, rbuf, mode);
+      hipLaunchKernelGGL((k_criterion<S, NC, true>), g, b, 0, st, P, D, rbuf, flags);
     else
-      hipLaunchKernelGGL((k_criterion<S, NC, false>), g, b, 0, st, P, D, rbuf, mode);
+      hipLaunchKernelGGL((k_criterion<S, NC, false>), g, b, 0, st, P, D, rbuf, flags);
     return hipGetLastError();
   }
 };
@@ -1513,27 +1388,18 @@ hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int fir
   return dispatch<InitL>(P, D, buf, first, count, from_dev, use_init, stream);
 }
 
-hipError_t launch_moments(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode, hipStream_t stream) {
-  return dispatch<MomentsL>(P, D, rbuf, pull, crit_mode, stream);
-}
-
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream) {
   hipLaunchKernelGGL(k_activate, dim3(1), dim3(1024), 0, stream, P, D, step);
   return hipGetLastError();
 }
 
-hipError_t launch_collide(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream) {
-  return dispatch<CollideL>(P, D, rbuf, pull, (float*)nullptr, (float*)nullptr, stream);
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream) {
+  return dispatch<FusedL>(P, D, rbuf, pull, stream);
 }
 
-hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, bool frontier_pass,
-                        hipStream_t stream) {
-  return dispatch<FusedL>(P, D, rbuf, pull, frontier_pass, stream);
-}
-
-hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int crit_mode,
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
                             hipStream_t stream) {
-  return dispatch<CriterionL>(P, D, rbuf, pull, crit_mode, stream);
+  return dispatch<CriterionL>(P, D, rbuf, pull, flags, stream);
 }
 
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u, float* umix,
@@ -1545,9 +1411,9 @@ hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, d
   return dispatch<MassL>(P, D, rbuf, pull, out, stream);
 }
 
-hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi, float* force,
-                               hipStream_t stream) {
-  return dispatch<CollideL>(P, D, rbuf, pull, psi, force, stream);
+hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots, float* psi,
+                               float* force, hipStream_t stream) {
+  return dispatch<DebugL>(P, D, rbuf, pull, psi_slots, psi, force, stream);
 }
 
 }  // namespace lbm

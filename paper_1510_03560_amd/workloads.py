@@ -193,6 +193,61 @@ def porous_injection(n: int = 192, seed: int = 0, porosity: float = 0.65, steps:
     return Case(f"porous{nx}x{ny}x{nz}-s{seed}", params, solid, None, None, act, steps, info)
 
 
+def porous_noise(n: int = 384, seed: int = 0, amp: float = 0.01, u_amp: float = 0.02,
+                 porosity: float = 0.65) -> Case:
+    """The porous-injection geometry and boundaries on a static mesh, with
+    every pore cell perturbed: each density is the background value times
+    (1 + amp (2U - 1)) and each velocity component u_amp (2U - 1), U uniform
+    from a PCG64 stream of seed + 1 (densities component-major, then the
+    velocities x, y, z; x fastest).  Every fluid cell then evolves from the
+    first step, which makes sampled comparisons meaningful anywhere.  The
+    default velocity amplitude is the injection speed of porous_injection."""
+    c = porous_injection(n, seed, porosity, steps=0, progressive=False)
+    N = c.N
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    bg = np.asarray(c.params["bg_rho"], dtype=np.float64)
+    rho0 = bg[:, None] * (1.0 + amp * (2.0 * rng.random((2, N)) - 1.0))
+    u0 = u_amp * (2.0 * rng.random((3, N)) - 1.0)
+    return Case(f"porousnoise{n}-s{seed}", c.params, c.solid, rho0, u0, None, 0, dict(c.info, amp=amp))
+
+
+def crop(case: Case, origin: tuple, size: tuple) -> tuple:
+    """A sub-box of a static case: the same parameters, geometry and initial
+    fields on [origin, origin + size).  Faces of the sub-box that lie on the
+    case's own faces keep their boundary kind; the others become walls.
+    Returns (Case, margins): margins[f] = 0 on a kept face, else 1 (an
+    artificial face).  Only cells farther than the dependency radius of the
+    compared step count from the artificial faces match the full run."""
+    p = case.params
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    ox, oy, oz = origin
+    sx, sy, sz = size
+    assert 0 <= ox and ox + sx <= nx and 0 <= oy and oy + sy <= ny and 0 <= oz and oz + sz <= nz
+    lo = (ox == 0, oy == 0, oz == 0)
+    hi = (ox + sx == nx, oy + sy == ny, oz + sz == nz)
+    bc = []
+    art = []
+    for d in range(3):
+        for side, kept in ((0, lo[d]), (1, hi[d])):
+            full = p["bc"][2 * d + side]
+            if full == PERIODIC and not (lo[d] and hi[d]):
+                raise ValueError("a sub-box cannot cut a periodic axis")
+            bc.append(full if kept else WALL)
+            art.append(0 if kept else 1)
+    q = dict(p, nx=sx, ny=sy, nz=sz, bc=tuple(bc))
+
+    def cut(a):
+        if a is None:
+            return None
+        lead = a.shape[:-1]
+        v = a.reshape(lead + (nz, ny, nx))[..., oz:oz + sz, oy:oy + sy, ox:ox + sx]
+        return np.ascontiguousarray(v).reshape(lead + (sx * sy * sz,))
+
+    sub = Case(f"{case.name}-crop{ox}_{oy}_{oz}", q, cut(case.solid), cut(case.rho0), cut(case.u0), None, 0,
+               dict(case.info))
+    return sub, tuple(art)
+
+
 def poiseuille(H: int = 64, nx: int = 16, nz: int = 16, gx: float = 1e-6, tau: float = 1.0) -> Case:
     """Single-component channel flow driven by a body force along x between
     walls on the y faces (H fluid rows), periodic along x and z."""

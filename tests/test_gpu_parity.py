@@ -162,6 +162,28 @@ def test_porous64_parity_vs_oracle(porous64):
     assert_parity(gp, r, label="porous64")
 
 
+def test_leak_counter_certifies_static_equality(lbm):
+    """The leak counter is the certificate that the progressive mesh
+    reproduces the static mesh.  A criterion threshold S = 1e-3 activates
+    blocks late: the counter fires and the fields differ from the static
+    mesh (the oracle shows the same).  With the literal one-cell boundary
+    shell the FP32 run may or may not leak, but a zero count must come with
+    bitwise-equal fields."""
+    case = W.porous_injection(48, 1, steps=60)
+    gs, ss, _ = run_gpu(lbm, case, 60, progressive=False)
+    late = W.Case("late", dict(case.params, S=1e-3), case.solid, None, None, case.active_blocks)
+    gl, sl, _ = run_gpu(lbm, late, 60)
+    print("S=1e-3 leak", sl["leak"], "blocks", sl["n_active"], flush=True)
+    assert sl["leak"] > 0 and sl["numeric_error"] == 0
+    assert not np.array_equal(gl[0], gs[0])
+    thin = W.Case("thin", dict(case.params, shell_width=1), case.solid, None, None, case.active_blocks)
+    gt, st, _ = run_gpu(lbm, thin, 60)
+    same = all(np.array_equal(a, b) for a, b in zip(gt[:3], gs[:3]))
+    print("shell 1 leak", st["leak"], "equal to static", same, flush=True)
+    if st["leak"] == 0:
+        assert same
+
+
 def test_extra_activation_changes_nothing(lbm, porous64):
     """Activating extra blocks between steps leaves every field bitwise
     unchanged (they take the rest state an inactive block stands for)."""
