@@ -70,6 +70,22 @@ __host__ __device__ constexpr float dir_w(int i) {
 
 constexpr float kThird = 1.0f / 3.0f;
 
+// e_i . (x, y, z) for a constant direction: the sum of the nonzero terms in
+// x, y, z order (the terms with a zero component are exactly zero, so this is
+// the full dot product without its multiplications by 0 and 1).
+template <int ex, int ey, int ez>
+__device__ __forceinline__ float edot(float x, float y, float z) {
+  static_assert(ex != 0 || ey != 0 || ez != 0, "rest direction");
+  const float tx = ex > 0 ? x : -x, ty = ey > 0 ? y : -y, tz = ez > 0 ? z : -z;
+  if constexpr (ex != 0 && ey != 0 && ez != 0) return (tx + ty) + tz;
+  if constexpr (ex != 0 && ey != 0) return tx + ty;
+  if constexpr (ex != 0 && ez != 0) return tx + tz;
+  if constexpr (ey != 0 && ez != 0) return ty + tz;
+  if constexpr (ex != 0) return tx;
+  if constexpr (ey != 0) return ty;
+  return tz;
+}
+
 template <int N, typename F>
 __host__ __device__ __forceinline__ void unroll(F&& fn) {
   if constexpr (N > 0) {
@@ -143,18 +159,21 @@ __device__ __forceinline__ Mom moments(const float f[kQ]) {
 // ------------------------------------------------------------------- EOS
 // Eq 7 (Peng-Robinson, denominator 1 + 2 b rho - b^2 rho^2) and Eq 6.  A
 // negative radicand gives psi = 0 and is reported through `clamped`.
+// The two terms of Eq 7 are put over their common denominator (one division)
+// and the square root is the hardware one (1 ulp).
 __device__ __forceinline__ float pseudo_potential(const Params& P, int a, float rho, bool& clamped) {
   const float g = P.g_self[a];
   clamped = false;
   if (g == 0.0f) return 0.0f;
   const float brho = P.b * rho;
-  const float p = (rho * P.RT) / (1.0f - brho) - (P.a_theta * rho * rho) / ((1.0f + 2.0f * brho) - brho * brho);
-  const float rad = (2.0f * (p - kThird * rho)) / (kThird * g);
+  const float d1 = 1.0f - brho, d2 = (1.0f + 2.0f * brho) - brho * brho;
+  const float p = ((rho * P.RT) * d2 - (P.a_theta * rho * rho) * d1) / (d1 * d2);
+  const float rad = (p - kThird * rho) * (6.0f / g);  // 2 (p - c_s^2 rho) / (c_s^2 g)
   if (!(rad >= 0.0f)) {
     clamped = true;
     return 0.0f;
   }
-  return sqrtf(rad);
+  return __builtin_amdgcn_sqrtf(rad);
 }
 
 // -------------------------------------------------------------- forcing
@@ -238,7 +257,7 @@ template <typename Emit>
 __device__ __forceinline__ void collide_emit(float omega, const float f[kQ], const Mom& m, const Vec3& F,
                                              Emit&& emit) {
   float inv = 0.0f;
-  if (m.rho > 0.0f) inv = 1.0f / m.rho;
+  if (m.rho > 0.0f) inv = __builtin_amdgcn_rcpf(m.rho);  // 1 ulp
   const float ux = m.jx * inv, uy = m.jy * inv, uz = m.jz * inv;
   const float dx = F.x * inv, dy = F.y * inv, dz = F.z * inv;
   const float sx = (ux + ux) + dx, sy = (uy + uy) + dy, sz = (uz + uz) + dz;  // u + v
@@ -256,9 +275,9 @@ __device__ __forceinline__ void collide_emit(float omega, const float f[kQ], con
     constexpr int ex = dir_ex(i), ey = dir_ey(i), ez = dir_ez(i);
     constexpr bool axis = i <= 6;
     const float w3 = axis ? wa3 : wd3, w45 = axis ? wa45 : wd45, we = axis ? wae : wde, wdv = axis ? wad : wdd;
-    const float eu = float(ex) * ux + float(ey) * uy + float(ez) * uz;
-    const float ed = float(ex) * dx + float(ey) * dy + float(ez) * dz;
-    const float es = float(ex) * sx + float(ey) * sy + float(ez) * sz;
+    const float eu = edot<ex, ey, ez>(ux, uy, uz);
+    const float ed = edot<ex, ey, ez>(dx, dy, dz);
+    const float es = edot<ex, ey, ez>(sx, sy, sz);
     const float even = we + w45 * (eu * eu);
     const float odd = w3 * eu;
     const float deven = wdv + w45 * (ed * es);
@@ -344,23 +363,36 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
   s.fidx[0] = own;
   if constexpr (REF) s.ridx[0] = own;
   const uint32_t own_second = own + plane;
-  unroll<kQ - 1>([&](auto K) {
-    constexpr int i = decltype(K)::value + 1;
-    constexpr bool second = !(i & 1);  // plane i is the second of its pair
-    if constexpr (!PULL) {
+  if constexpr (!PULL) {
+    unroll<kQ - 1>([&](auto K) {
+      constexpr int i = decltype(K)::value + 1;
+      constexpr bool second = !(i & 1);  // plane i is the second of its pair
       s.fidx[i] = second ? own_second : own;
       if constexpr (REF) s.ridx[i] = own;
-    } else {
-      constexpr int ex = dir_ex(i), ey = dir_ey(i), ez = dir_ez(i);
-      const uint32_t w = pa.ax[1 - ex] + pa.ay[1 - ey] + pa.az[1 - ez];  // source = x - e_i
-      const uint32_t src_cell = ((uint32_t)nslot[w >> 16] << 12) | (w & 0xFFFFu);
+    });
+  } else {
+    // all slot lookups first (independent table reads), then the addresses
+    uint32_t w[kQ];
+    int slot[kQ];
+    unroll<kQ - 1>([&](auto K) {
+      constexpr int i = decltype(K)::value + 1;
+      w[i] = pa.ax[1 - dir_ex(i)] + pa.ay[1 - dir_ey(i)] + pa.az[1 - dir_ez(i)];  // source = x - e_i
+    });
+    unroll<kQ - 1>([&](auto K) {
+      constexpr int i = decltype(K)::value + 1;
+      slot[i] = nslot[w[i] >> 16];
+    });
+    unroll<kQ - 1>([&](auto K) {
+      constexpr int i = decltype(K)::value + 1;
+      constexpr bool second = !(i & 1);  // plane i is the second of its pair
+      const uint32_t src_cell = ((uint32_t)slot[i] << 12) | (w[i] & 0xFFFFu);
       const bool bounce = (m >> i) & 1u;
       // bounced: the cell's own population of the opposite direction, which
       // is the other plane of the pair
       s.fidx[i] = bounce ? (second ? own : own_second) : (second ? src_cell + plane : src_cell);
       if constexpr (REF) s.ridx[i] = bounce ? own : src_cell;
-    }
-  });
+    });
+  }
 }
 
 // Populations of component a arriving at the cell (decoded to FP32).
@@ -391,7 +423,6 @@ struct BlockCtx {
   int nbk[27];
   unsigned cand;
   unsigned fired;
-  int has_bc;  // the block touches a face with inlet or outlet nodes
 };
 
 __device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, int blk, BlockCtx& ctx) {
@@ -412,10 +443,6 @@ __device__ __forceinline__ void setup_block(const Params& P, const Buffers& D, i
   if (t == 0) {
     ctx.cand = (unsigned)bal;
     ctx.fired = 0u;
-    const bool on[6] = {bx == 0, bx == P.nbx - 1, by == 0, by == P.nby - 1, bz == 0, bz == P.nbz - 1};
-    int hb = 0;
-    for (int f = 0; f < 6; ++f) hb |= (on[f] && (P.bc[f] == kInletFace || P.bc[f] == kOutletFace)) ? 1 : 0;
-    ctx.has_bc = hb;
   }
 }
 
@@ -821,8 +848,6 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
 // state: they contribute psi_rest without being pulled.  Psi never goes to
 // memory; the populations are read once (plus the ring and the two halo
 // planes, which neighbouring blocks also read) and written once.
-// Boundary nodes impose their state in a post-pass (blocks on an inlet or
-// outlet face only).
 constexpr int kFusedThreads = 384;
 constexpr int kPsiRing = 4;
 constexpr int kFoot = kH * kH;  // 324 columns
@@ -834,6 +859,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
   if (s >= n_active) return;
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
+  __shared__ uint32_t mask_s[2][kFusedThreads];
   __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
   setup_block(P, D, D.slot_block[s], ctx);
   if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
@@ -879,28 +905,46 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
   float fp[NC][kQ];   // populations of this column's cell one plane back
   float rp[NC];       // and its densities
   uint32_t mp = 0u;   // and its mask
-  bool collide_next = false;
+  bool store_next = false;
   unsigned numeric = 0u, clamps = 0u;
+  // Masks are loaded one plane ahead and handed to the next plane through
+  // LDS: the load completes while the plane's pulls are waited for, so the
+  // pull addresses of a plane never wait for a memory round trip of their
+  // own.  Cells outside the active blocks read as solid (no pulls, rest psi).
+  // Every thread loads and hands over a mask at every plane (addresses in
+  // bounds also past the last plane and in the rest slot), so that no load
+  // is pending on one path and not on another.
+  auto mask_load = [&](int z) -> uint32_t {
+    const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
+    return ld(D.mask, ((uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15)) * 4u);
+  };
+  auto in_mesh = [&](int z) { return col && ctx.nslot[dxy + 9 * sgn_out(z)] != P.capacity; };
+  constexpr uint32_t kNoCell = (uint32_t)kSolid << kKindShift;
+  {
+    const uint32_t raw = mask_load(-1);
+    mask_s[0][t] = in_mesh(-1) ? raw : kNoCell;
+  }
 #pragma unroll 1
   for (int k = 0; k < kH; ++k) {
     const int z = k - 1;
+    const bool own = interior && z >= 0 && z < kB;
+    const uint32_t m = mask_s[k & 1][t];
+    const uint32_t m_ahead = mask_load(z + 1);
     // ---- plane z: pull, moments, psi
     float f[NC][kQ];
     float rho[NC];
-    uint32_t m = 0u;
-    bool fluid = false;
     if (col) {
       float psi[NC];
       const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
       const uint32_t cell = (uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15);
-      const bool own = interior && z >= 0 && z < kB;
 #pragma unroll
       for (int a = 0; a < NC; ++a) psi[a] = P.psi_rest[a];
       if (slot != P.capacity) {
-        m = ld(D.mask, cell * 4u);
         const uint32_t kind = (m >> kKindShift) & 3u;
-        if (kind == kFluid) {
-          fluid = true;
+        // fluid cells, and (FP16 store) the block's own boundary nodes, whose
+        // density is the reference of what they store
+        const bool pull = kind == kFluid || (S::kRef && own && kind != kSolid);
+        if (pull) {
           Sources<S::kRef> src;
           pull_axes_z(z, pa);
           sources<PULL, S::kRef>(pa, cell, m, plane, ctx.nslot, src);
@@ -908,6 +952,11 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
           for (int a = 0; a < NC; ++a) {
             gather<S>(fb, plane, a, src, rref, f[a]);
             rho[a] = moments(f[a]).rho;
+          }
+        }
+        if (kind == kFluid) {
+#pragma unroll
+          for (int a = 0; a < NC; ++a) {
             bool cl;
             psi[a] = pseudo_potential(P, a, rho[a], cl);
             if (own) {
@@ -923,83 +972,67 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
 #pragma unroll
       for (int a = 0; a < NC; ++a) psi_s[k % kPsiRing][a][hp] = psi[a];
     }
+    mask_s[(k + 1) & 1][t] = in_mesh(z + 1) ? m_ahead : kNoCell;
     __syncthreads();
-    // ---- plane z - 1: forces, collision, store (interior fluid cells)
-    if (collide_next) {
+    // ---- plane z - 1: every cell of the block is stored, so that each
+    // written cache line is complete (a partial line costs the memory a
+    // read-modify-write).  Fluid cells collide; inlet and outlet nodes impose
+    // their state; solid cells take the rest state, which nothing reads.
+    if (store_next) {
       const int zc = z - 1;
       const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * zc);
-      const int sl[3] = {(k + 2) % kPsiRing, (k + 3) % kPsiRing, k % kPsiRing};  // planes zc-1, zc, zc+1
-      float psi_c[NC];
+      const uint32_t kind = (mp >> kKindShift) & 3u;
+      if (kind == kFluid) {
+        const int sl[3] = {(k + 2) % kPsiRing, (k + 3) % kPsiRing, k % kPsiRing};  // planes zc-1, zc, zc+1
+        float psi_c[NC];
 #pragma unroll
-      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[sl[1]][a][hp];
-      Vec3 F[NC];
-      interaction_forces<NC>(P, psi_c,
-                             [&](int a, int i) {
-                               const int hn = hp + dir_ex(i) + kH * dir_ey(i);
-                               const bool solid_nb = (mp >> dir_opp(i)) & 1u;  // x + e_i solid or outside
-                               return solid_nb ? psi_c[a] : psi_s[sl[1 + dir_ez(i)]][a][hn];
-                             },
-                             F);
+        for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[sl[1]][a][hp];
+        Vec3 F[NC];
+        interaction_forces<NC>(P, psi_c,
+                               [&](int a, int i) {
+                                 const int hn = hp + dir_ex(i) + kH * dir_ey(i);
+                                 const bool solid_nb = (mp >> dir_opp(i)) & 1u;  // x + e_i solid or outside
+                                 return solid_nb ? psi_c[a] : psi_s[sl[1 + dir_ez(i)]][a][hn];
+                               },
+                               F);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        Mom mo = moments(fp[a]);
-        const float rr = rp[a];  // FP16 reference: this cell's density of this step
-        if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
-        collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho), [&](auto I, float v) {
-          constexpr int i = decltype(I)::value;
-          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-          constexpr bool second = i != 0 && !(i & 1);
-          const typename S::T enc = S::encode(v, dir_w(i) * rr);
-          st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-        });
+        for (int a = 0; a < NC; ++a) {
+          Mom mo = moments(fp[a]);
+          const float rr = rp[a];  // FP16 reference: this cell's density of this step
+          if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
+          collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho), [&](auto I, float v) {
+            constexpr int i = decltype(I)::value;
+            constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+            constexpr bool second = i != 0 && !(i & 1);
+            const typename S::T enc = S::encode(v, dir_w(i) * rr);
+            st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+          });
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          // FP16 reference: a boundary node's own density of this step
+          const float rr = kind == kSolid ? P.rho_ref_rest[a] : rp[a];
+          if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
+          unroll<kQ>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+            constexpr bool second = i != 0 && !(i & 1);
+            const typename S::T enc = S::encode(kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], dir_w(i) * rr);
+            st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+          });
+        }
       }
     }
-    // ---- keep plane z for its collision at the next iteration
-    collide_next = interior && fluid && z >= 0 && z < kB;
-    if (collide_next) {
+    // ---- keep plane z for its store at the next iteration
+    store_next = own;
+    if (own) {
       mp = m;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         rp[a] = rho[a];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) fp[a][i] = f[a][i];
-      }
-    }
-  }
-  // ---- boundary nodes impose their state (blocks on an inlet/outlet face)
-  if (ctx.has_bc && interior) {
-    PullAxes pb = pa;
-#pragma unroll 1
-    for (int z = 0; z < kB; ++z) {
-      const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * z);
-      const uint32_t m = ld(D.mask, cid * 4u);
-      const uint32_t kind = (m >> kKindShift) & 3u;
-      if (kind != kInlet && kind != kOutlet) continue;
-      float rr[NC];
-#pragma unroll
-      for (int a = 0; a < NC; ++a) rr[a] = 0.0f;
-      if constexpr (S::kRef) {
-        // the reference is the node's own density of this step
-        Sources<S::kRef> src;
-        pull_axes_z(z, pb);
-        sources<PULL, S::kRef>(pb, cid, m, plane, ctx.nslot, src);
-#pragma unroll
-        for (int a = 0; a < NC; ++a) {
-          float f[kQ];
-          gather<S>(fb, plane, a, src, rref, f);
-          rr[a] = moments(f).rho;
-          st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        unroll<kQ>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-          constexpr bool second = i != 0 && !(i & 1);
-          const typename S::T enc = S::encode(kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], dir_w(i) * rr[a]);
-          st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-        });
       }
     }
   }
