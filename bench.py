@@ -59,6 +59,73 @@ def measured_traffic():
     return d.get("fused_step_bytes_per_launch")
 
 
+STEP_KERNEL = "k_fused<lbm::(anonymous namespace)::StoreF32, 2, true>"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 1 << 30
+
+
+def _short(name: str) -> str:
+    return name.replace("lbm::(anonymous namespace)::", "").split("(lbm::Params")[0].replace("void ", "")
+
+
+def summarize_trace(trace_csv: str, last: int) -> str:
+    """Text summary of a rocprofv3 --kernel-trace run of this script: per
+    kernel calls / average / total, and the average of the step kernel over
+    its last `last` launches (the full-mesh launches the roofline is timed on)."""
+    import csv
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    by = {}
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        by.setdefault(r["Kernel_Name"], []).append(d)
+    out = ["| kernel | calls | average us | total ms |", "|---|---|---|---|"]
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {_short(k)} | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) * 1e-3:.3f} |")
+    step = [v for k, v in by.items() if STEP_KERNEL in k.replace("void ", "")]
+    if step:
+        tail = step[0][-last:]
+        out.append("")
+        out.append(f"step kernel, last {len(tail)} launches (full mesh): average {sum(tail) / len(tail):.2f} us, "
+                   f"min {min(tail):.2f} us, max {max(tail):.2f} us")
+    return "\n".join(out)
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, last: int) -> dict:
+    """HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled by what the same counter
+    reads for a 1 GiB device copy run in the same process (--calibrate)."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        by = {}
+        for r in rows:
+            by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return by
+
+    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    cf = max(v for k, vs in f.items() if COPY_KERNEL in k for v in vs)
+    cw = max(v for k, vs in w.items() if COPY_KERNEL in k for v in vs)
+    fetch_scale = COPY_BYTES / (cf * 1024.0)   # bytes moved per byte counted
+    write_scale = COPY_BYTES / (cw * 1024.0)
+    sf = next(vs for k, vs in f.items() if STEP_KERNEL in k.replace("void ", ""))[-last:]
+    sw = next(vs for k, vs in w.items() if STEP_KERNEL in k.replace("void ", ""))[-last:]
+    fb = float(np.median(sf)) * 1024.0 * fetch_scale
+    wb = float(np.median(sw)) * 1024.0 * write_scale
+    return {
+        "kernel": _short(STEP_KERNEL),
+        "kernel_source_sha256": kernel_source_hash(),
+        "launches": len(sf),
+        "fetch_kib_per_launch_raw": float(np.median(sf)),
+        "write_kib_per_launch_raw": float(np.median(sw)),
+        "copy_1gib_fetch_kib": cf, "copy_1gib_write_kib": cw,
+        "fetch_factor": fetch_scale, "write_factor": write_scale,
+        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+        "fused_step_bytes_per_launch": fb + wb,
+    }
+
+
 def active_cells_per_step(trace: np.ndarray, n0: int, t0: int, k: int) -> np.ndarray:
     """Active blocks during each of steps t0 .. t0+k-1, from the activation
     trace (a block recorded at step s takes part from step s on)."""
@@ -92,7 +159,19 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print the summary of a rocprofv3 kernel trace of this script and exit")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the step kernel's HBM bytes per launch from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--last", type=int, default=20,
+                    help="with --summarize-*: number of final step-kernel launches to use (full mesh)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.last))
+        return
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc, args.last), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (the whole lattice lives on one MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
