@@ -148,6 +148,74 @@ def fluid_cells_of_active(case, trace, t) -> int:
     return int(fluid[act].sum())
 
 
+def run_channels(args):
+    """The channel workload (1024 x 1024 x 128 by default): progressive and
+    static runs of the same steps, with the meshed blocks and their bytes
+    sampled along the way (the paper's memory-over-time comparison)."""
+    import torch
+    from paper_1510_03560_amd import lbm
+    from paper_1510_03560_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    nx, ny, nz = args.channel_shape
+    case = W.channel_network(nx, ny, nz, seed=args.seed, n_live=args.channel_tubes)
+    K, Wm, chunk = args.steps, args.warmup, args.sample_every
+    out = {}
+    for progressive in (True, False):
+        sim = lbm.Simulation(case, progressive=progressive)
+        sim.step(Wm)
+        torch.cuda.synchronize()
+        st0 = sim.stats()
+        ms, series, done = 0.0, [], 0
+        cells = 0
+        while done < K:
+            n = min(chunk, K - done)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(n)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            st = sim.stats()
+            done += n
+            # cells of active blocks, counted per step from the activation trace
+            tr = sim.trace()
+            steps_act = tr[:, 0] if len(tr) else np.zeros(0)
+            t0 = Wm + done - n
+            for j in range(n):
+                cells += 4096 * int(np.count_nonzero(steps_act <= t0 + j)) if progressive else 4096 * st["n_active"]
+            series.append([Wm + done, st["n_active"], st["bytes_active"]])
+        out[progressive] = dict(ms=ms, stats=st, series=series, cells=cells, start=st0["n_active"])
+        sim.close()
+        print(f"bench: channels {'progressive' if progressive else 'static'} {K} steps {ms:.1f} ms, "
+              f"blocks {st['n_active']}/{st['n_fluid_blocks']}", file=sys.stderr, flush=True)
+    p_, s_ = out[True], out[False]
+    peak_p = max(b for _, _, b in p_["series"])
+    res = {
+        "metric": "active-cell MLUPS",
+        "value": round(p_["cells"] / (p_["ms"] * 1e-3) / 1e6, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": round(p_["ms"] / K, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"channel network {nx}x{ny}x{nz}, {args.channel_tubes} open and "
+                               f"{args.channel_tubes} sealed tubes, progressive mesh from the inlet blocks, FP32",
+                   "lattice": [nx, ny, nz], "block": 16, "components": 2, "seed": args.seed,
+                   "fluid_blocks": int(p_["stats"]["n_fluid_blocks"])},
+        "static_ms_per_step": round(s_["ms"] / K, 4),
+        "progressive_over_static_time": round(p_["ms"] / s_["ms"], 4),
+        "leak": int(p_["stats"]["leak"]),
+        "memory": {
+            "static_bytes_active": int(s_["stats"]["bytes_active"]),
+            "progressive_bytes_active_peak": int(peak_p),
+            "progressive_over_static": round(peak_p / s_["stats"]["bytes_active"], 4),
+            "series_step_blocks_bytes": p_["series"],
+        },
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +233,11 @@ def main():
                     help="print the step kernel's HBM bytes per launch from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--last", type=int, default=20,
                     help="with --summarize-*: number of final step-kernel launches to use (full mesh)")
+    ap.add_argument("--workload", choices=["porous", "channels"], default="porous",
+                    help="porous: the 192^3 porous injection (default); channels: the channel network")
+    ap.add_argument("--channel-shape", type=int, nargs=3, default=[1024, 1024, 128])
+    ap.add_argument("--channel-tubes", type=int, default=8)
+    ap.add_argument("--sample-every", type=int, default=100)
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.last))
@@ -176,6 +249,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (the whole lattice lives on one MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "channels":
+        run_channels(args)
+        return
 
     import torch
     from paper_1510_03560_amd import lbm

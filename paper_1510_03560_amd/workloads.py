@@ -248,6 +248,63 @@ def crop(case: Case, origin: tuple, size: tuple) -> tuple:
     return sub, tuple(art)
 
 
+def channel_network(nx: int = 1024, ny: int = 1024, nz: int = 128, seed: int = 0, n_live: int = 8,
+                    block: int = 16, progressive: bool = True, steps: int = 0) -> Case:
+    """Channels carved through a solid slab (a stand-in for the paper's channel
+    geometry, section 5.2, whose figure is missing): n_live wavy tubes run along
+    x from the inlet face to the outlet face, and beside each of them a sealed
+    tube of the same kind holds fluid that the injection never reaches.
+
+    With spacing d = ny / n_live, live tube k is centred on y = (k + 1/4) d and
+    sealed tube k on y = (k + 3/4) d, both near z = nz / 2.  Along x each
+    tube's centre performs a bounded random walk (steps of at most 1 cell
+    every 8 cells, within +-d/16 in y and +-nz/8 in z) and its half-widths
+    are drawn per tube in [d/32, d/16] (y) and [nz/32, nz/16] (z), at least 2
+    cells, so neighbouring tubes stay at least d/4 apart.  Sealed tubes span
+    x in [nx/16, 15 nx/16).  Draws come from PCG64(seed) in the order: per
+    tube, live then sealed, its half-widths, then its walk steps.  Boundaries,
+    densities and the initial mesh are those of porous_injection (inlet at
+    x = 0, outlet at x = nx - 1, walls on y and z, the inlet blocks holding
+    fluid meshed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    solid = np.ones((nz, ny, nx), dtype=np.uint8)
+    sp = ny / n_live
+    wy = max(1, int(sp / 16))
+    wz = max(1, nz // 8)
+
+    def carve(yc0, x0, x1):
+        hy = max(2, int(rng.integers(max(2, int(sp / 32)), max(3, int(sp / 16)) + 1)))
+        hz = max(2, int(rng.integers(max(2, nz // 32), max(3, nz // 16) + 1)))
+        steps_y = rng.integers(-1, 2, size=(x1 - x0 + 7) // 8)
+        steps_z = rng.integers(-1, 2, size=(x1 - x0 + 7) // 8)
+        dy = dz = 0
+        for j, x in enumerate(range(x0, x1)):
+            if x > x0 and (x - x0) % 8 == 0:
+                dy = int(np.clip(dy + steps_y[(x - x0) // 8], -wy, wy))
+                dz = int(np.clip(dz + steps_z[(x - x0) // 8], -wz, wz))
+            yc = int(round(yc0)) + dy
+            zc = nz // 2 + dz
+            solid[max(0, zc - hz):min(nz, zc + hz + 1), max(0, yc - hy):min(ny, yc + hy + 1), x] = 0
+
+    for k in range(n_live):
+        carve((k + 0.25) * sp, 0, nx)
+        carve((k + 0.75) * sp, nx // 16, nx - nx // 16)
+    solid = solid.reshape(-1)
+    params = dict(FLUID, nx=nx, ny=ny, nz=nz, block=block, ncomp=2, shell_width=2, S=0.0,
+                  bc=(INLET, OUTLET, WALL, WALL, WALL, WALL), body=((0.0,) * 3,) * 2,
+                  inlet_rho=(6.5, 0.1), inlet_u=(0.02, 0.0, 0.0), bg_rho=(0.38, 0.38))
+    nbx, nby, nbz = nx // block, ny // block, nz // block
+    fluid_b = (solid.reshape(nbz, block, nby, block, nbx, block) == 0).any(axis=(1, 3, 5))
+    act = None
+    if progressive:
+        a = np.zeros((nbz, nby, nbx), dtype=np.uint8)
+        a[:, :, 0] = fluid_b[:, :, 0]
+        act = a.reshape(-1)
+    info = dict(seed=seed, porosity=float(1.0 - solid.mean()), n_live=n_live,
+                fluid_blocks=int(fluid_b.sum()))
+    return Case(f"channels{nx}x{ny}x{nz}-s{seed}", params, solid, None, None, act, steps, info)
+
+
 def poiseuille(H: int = 64, nx: int = 16, nz: int = 16, gx: float = 1e-6, tau: float = 1.0) -> Case:
     """Single-component channel flow driven by a body force along x between
     walls on the y faces (H fluid rows), periodic along x and z."""
