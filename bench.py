@@ -6,9 +6,11 @@ oracle timed beside it.
 
 Workload: porous injection, 192^3 lattice in 16^3 blocks, random
 non-overlapping spheres of radius 4-12 at porosity 0.65, liquid injected at
-x = 0, only the inlet blocks meshed at t = 0, FP32.  A step is one call of
-the whole hot path: moments, pseudo-potential and criterion, activation,
-initialisation of new blocks, forces, collision and streaming.
+x = 0, only the inlet blocks meshed at t = 0, FP32, 10000 steps, against a
+static full-grid run of the same steps.  A step is one call of the whole hot
+path: criterion, activation, initialisation of new blocks, moments,
+pseudo-potential, forces, collision and streaming.  --size 384 --store f16
+gives the precision configuration (FP16-deviation store).
 
 Prints one JSON line.  value = active cells updated per second (millions),
 summed over the K timed steps (cells of active blocks, solid or not).
@@ -31,6 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # block (two components, FP32): 2 x 19 populations read once and written once
 # (304 B) and the cell's mask word (4 B); the pseudo-potential stays in LDS.
 K2_BYTES_PER_FLUID_CELL = 2 * 19 * 4 * 2 + 4
+# FP16-deviation store: 2 x 19 populations at 2 B read and written (152 B),
+# the two reference densities read and written (16 B) and the mask (4 B)
+K2_BYTES_PER_FLUID_CELL_F16 = 2 * 19 * 2 * 2 + 16 + 4
 # per solid cell of an active block the kernel reads only the mask word
 K2_BYTES_PER_SOLID_CELL = 4
 
@@ -216,12 +221,102 @@ def run_channels(args):
     print(json.dumps(res), flush=True)
 
 
+def run_proposal(args):
+    """The learned activation proposal: training data from criterion-only
+    progressive runs (porous injection at 128^3, seeds 0..n_train-1), the
+    network trained on the GPU with the library's kernels, precision and
+    recall on held-out seeds at 256^3 (labels: activated by the criterion
+    within K = 20 steps), and time with the proposal against the
+    criterion-only and static runs of the same steps (fields compared bit for
+    bit)."""
+    import torch
+    from paper_1510_03560_amd import lbm, mlp
+    from paper_1510_03560_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    K = 20
+    t0 = time.time()
+    Xs, Ys = [], []
+    for seed in range(args.train_seeds):
+        X, Y, _, _ = mlp.collect(W.porous_injection(128, seed, steps=args.train_steps), args.train_steps,
+                                 every=2, K=K)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = np.concatenate(Xs), np.concatenate(Ys)
+    print(f"bench: proposal training set {len(Y)} samples ({int(Y.sum())} positive) in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    p0 = mlp.standardise(mlp.initial_params(0), X)
+    t1 = time.time()
+    params, hist = mlp.train(X, Y, p0, epochs=args.epochs, batch=512, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    print(f"bench: trained {args.epochs} epochs in {train_s:.1f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
+          file=sys.stderr, flush=True)
+    # held-out precision / recall
+    tp = fp = fn = 0
+    for seed in range(1000, 1000 + args.test_seeds):
+        Xt, Yt, _, _ = mlp.collect(W.porous_injection(256, seed, steps=args.test_steps), args.test_steps,
+                                   every=4, K=K)
+        pred = mlp.predict(params, Xt) > args.threshold
+        tp += int(np.sum(pred & (Yt > 0.5)))
+        fp += int(np.sum(pred & (Yt <= 0.5)))
+        fn += int(np.sum(~pred & (Yt > 0.5)))
+    precision = tp / max(1, tp + fp)
+    recall = tp / max(1, tp + fn)
+    # time to solution on one held-out seed
+    case = W.porous_injection(256, 1000, steps=args.steps)
+    times, fields = {}, {}
+    for mode in ("criterion", "proposal", "static"):
+        sim = lbm.Simulation(case, progressive=mode != "static")
+        if mode == "proposal":
+            mlp.set_proposal(sim, params, threshold=args.threshold)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        times[mode] = e0.elapsed_time(e1)
+        rho = torch.empty(2 * case.N, dtype=torch.float32, device="cuda")
+        lbm.lbm_moments_device(sim.h, rho.data_ptr(), 0, 0)
+        st = sim.stats()
+        sim.close()
+        torch.cuda.synchronize()
+        fields[mode] = (rho, st)
+    identical = bool(torch.equal(fields["criterion"][0], fields["proposal"][0])
+                     and torch.equal(fields["criterion"][0], fields["static"][0]))
+    res = {
+        "metric": "learned activation proposal: precision / recall and time to solution",
+        "value": round(times["criterion"] / times["proposal"], 4),
+        "unit": "speed-up of the proposal run over the criterion-only run",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": round(times["proposal"] / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"porous injection, train {args.train_seeds} seeds at 128^3 x {args.train_steps} "
+                               f"steps, test {args.test_seeds} held-out seeds at 256^3 x {args.test_steps} steps, "
+                               f"K = {K}, threshold {args.threshold}"},
+        "train_samples": int(len(Y)), "train_positive": int(Y.sum()), "train_seconds": round(train_s, 2),
+        "loss_first_last_epoch": [round(hist[0], 5), round(hist[-1], 5)],
+        "precision": round(precision, 4), "recall": round(recall, 4),
+        "tp_fp_fn": [tp, fp, fn],
+        "ms_criterion_only": round(times["criterion"], 2), "ms_proposal": round(times["proposal"], 2),
+        "ms_static": round(times["static"], 2),
+        "fields_bit_identical": identical,
+        "leak": [int(fields["criterion"][1]["leak"]), int(fields["proposal"][1]["leak"])],
+        "blocks_end": [int(fields[m][1]["n_active"]) for m in ("criterion", "proposal", "static")],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--size", type=int, default=192)
+    ap.add_argument("--store", choices=["f32", "f16"], default="f32",
+                    help="population storage: FP32, or FP16 deviations (arithmetic is FP32 in both)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -233,8 +328,15 @@ def main():
                     help="print the step kernel's HBM bytes per launch from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--last", type=int, default=20,
                     help="with --summarize-*: number of final step-kernel launches to use (full mesh)")
-    ap.add_argument("--workload", choices=["porous", "channels"], default="porous",
-                    help="porous: the 192^3 porous injection (default); channels: the channel network")
+    ap.add_argument("--workload", choices=["porous", "channels", "proposal"], default="porous",
+                    help="porous: the 192^3 porous injection (default); channels: the channel network; "
+                         "proposal: train and evaluate the learned activation proposal")
+    ap.add_argument("--train-seeds", type=int, default=32)
+    ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--test-seeds", type=int, default=8)
+    ap.add_argument("--test-steps", type=int, default=600)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--threshold", type=float, default=0.5)
     ap.add_argument("--channel-shape", type=int, nargs=3, default=[1024, 1024, 128])
     ap.add_argument("--channel-tubes", type=int, default=8)
     ap.add_argument("--sample-every", type=int, default=100)
@@ -251,6 +353,9 @@ def main():
         sys.exit(2)
     if args.workload == "channels":
         run_channels(args)
+        return
+    if args.workload == "proposal":
+        run_proposal(args)
         return
 
     import torch
@@ -273,8 +378,10 @@ def main():
           file=sys.stderr, flush=True)
     K, Wm = args.steps, args.warmup
 
+    store = lbm.STORE_F32 if args.store == "f32" else lbm.STORE_F16DEV
+
     def timed_run(progressive: bool):
-        sim = lbm.Simulation(case, progressive=progressive)
+        sim = lbm.Simulation(case, progressive=progressive, store=store)
         sim.step(Wm)
         torch.cuda.synchronize()
         st0 = sim.stats()
@@ -316,7 +423,8 @@ def main():
     k2_ms = tot / max(cnt, 1)
     fluid_full = fluid_cells_of_active(case.static_twin(), np.zeros((0, 2), np.int32), 0)
     cells_full = stat["stats"]["n_active"] * 4096
-    k2_bytes = fluid_full * K2_BYTES_PER_FLUID_CELL + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
+    per_fluid = K2_BYTES_PER_FLUID_CELL if args.store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
+    k2_bytes = fluid_full * per_fluid + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
 
     cells_p = int(prog["active_blocks_per_step"].sum()) * 4096
@@ -337,8 +445,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"porous injection {n}^3, 16^3 blocks, spheres r 4-12, porosity "
-                        f"{case.info['porosity']:.3f}, progressive mesh from the inlet blocks, FP32",
+                        f"{case.info['porosity']:.3f}, progressive mesh from the inlet blocks, "
+                        + ("FP32" if args.store == "f32" else "FP32 arithmetic, FP16-deviation store"),
             "lattice": [n, n, n], "block": 16, "components": 2, "seed": args.seed,
+            "store": args.store,
             "active_blocks_start": int(prog["active_blocks_per_step"][0]),
             "active_blocks_end": int(prog["active_blocks_per_step"][-1]),
             "fluid_blocks": int(prog["stats"]["n_fluid_blocks"]),
@@ -356,7 +466,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic() if (n == 192 and args.store == "f32") else None,
             "bytes_per_launch": int(k2_bytes),
             "launch_ms": round(k2_ms, 5),
         },

@@ -194,12 +194,12 @@ int lbm_debug_fields(lbm_t* h, int which, double* out);
 /* Per-kernel GPU timing.  lbm_timing_enable(h, 1) records HIP events around
  * every kernel lbm_step launches (on the handle's stream); lbm_timing_read
  * waits for the stream and returns, per kernel k < n (names from
- * lbm_kernel_name: criterion, activate, init_blocks, fused_step), the launch
- * count and total milliseconds, then resets. */
+ * lbm_kernel_name: criterion, activate, init_blocks, fused_step, propose),
+ * the launch count and total milliseconds, then resets. */
 int lbm_timing_enable(lbm_t* h, int enable);
 int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n);
 const char* lbm_kernel_name(int32_t k);
-#define LBM_NUM_KERNELS 4
+#define LBM_NUM_KERNELS 5
 
 /* Releases every resource of the handle (waits for the stream). */
 int lbm_destroy(lbm_t* h);

@@ -8,8 +8,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_api.cpp")]
-HEADERS = [os.path.join(CSRC, "lbm_internal.h"), os.path.join(ROOT, "include", "lbm.h")]
+SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_api.cpp"),
+           os.path.join(CSRC, "mlp_kernels.hip")]
+HEADERS = [os.path.join(CSRC, "lbm_internal.h"), os.path.join(ROOT, "include", "lbm.h"),
+           os.path.join(ROOT, "include", "lbm_mlp.h")]
 
 # No floating-point contraction: the same expression must round the same way
 # in every kernel (the rest state is a bitwise fixed point of the update).

@@ -15,13 +15,15 @@
 
 #include "lbm.h"
 #include "lbm_internal.h"
+#include "lbm_mlp.h"
 
 using namespace lbm;
 
 namespace {
 
 constexpr int kTraceCap = 1 << 20;
-const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step"};
+const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step",
+                                                   "propose"};
 
 std::string g_create_error;
 
@@ -47,6 +49,16 @@ struct lbm_handle {
   float* init_rho = nullptr;
   float* init_u = nullptr;
   int32_t* ids_dev = nullptr;
+  std::vector<float> bfrac_h;     // fluid fraction per block
+  float* mlp_dev = nullptr;       // proposal network parameters (LBM_MLP_NPARAMS)
+  float prop_thr = 0.5f;
+  bool prop_enabled = false;
+  // once every block holding fluid is active the criterion has no candidates
+  // left: the step then skips it (and activation), exactly
+  bool mesh_complete = false;
+  int32_t* nact_pinned = nullptr;  // pinned host copy of n_active
+  hipEvent_t nact_ev = nullptr;
+  bool nact_pending = false;
   int ids_cap = 0;
   double* mass_dev = nullptr;
   float* scratch_f = nullptr;  // small device scratch (rest state)
@@ -349,6 +361,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   // block classification on the host
   h->bfluid_h.assign(P.nb, 0);
   h->binlet_h.assign(P.nb, 0);
+  h->bfrac_h.assign(P.nb, 0.0f);
   h->fluid_cells = 0;
   for (int z = 0; z < P.nz; ++z)
     for (int y = 0; y < P.ny; ++y)
@@ -357,6 +370,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
         if (solid && solid[n]) continue;
         const int b = x / kB + P.nbx * (y / kB + P.nby * (z / kB));
         h->bfluid_h[b] = 1;
+        h->bfrac_h[b] += 1.0f / (float)kCells;
         h->fluid_cells++;
         const bool on[6] = {x == 0, x == P.nx - 1, y == 0, y == P.ny - 1, z == 0, z == P.nz - 1};
         for (int f = 0; f < 6; ++f)
@@ -380,14 +394,19 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * plane) : nullptr;
   D.block_slot = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.slot_block = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
+  D.order = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
   D.bfluid = (uint8_t*)dev_alloc(h, P.nb);
   D.solid = (uint8_t*)dev_alloc(h, (size_t)N);
   D.request = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.expose = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
+  D.act_step = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
+  D.bfrac = (float*)dev_alloc(h, sizeof(float) * P.nb);
+  D.cand = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
   if (!D.f[0] || !D.f[1] || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
-      !D.slot_block || !D.bfluid || !D.solid || !D.request || !D.expose || !D.trace)
+      !D.slot_block || !D.order || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
+      !D.cand || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
   h->slot_bytes = (int64_t)kCells * ((int64_t)2 * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) + 4 +
                                      (h->user.progressive ? 12 * P.ncomp : 0));
@@ -421,6 +440,13 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   HIP_TRY(h, hipMemcpy(D.bfluid, h->bfluid_h.data(), P.nb, hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemsetAsync(D.request, 0, sizeof(int32_t) * P.nb, h->stream));
   HIP_TRY(h, hipMemsetAsync(D.expose, 0, sizeof(int32_t) * P.nb, h->stream));
+  HIP_TRY(h, hipMemsetAsync(D.act_step, 0xFF, sizeof(int32_t) * P.nb, h->stream));  // -1: never activated
+  if (h->user.progressive) {
+    HIP_TRY(h, hipHostMalloc((void**)&h->nact_pinned, sizeof(int32_t), hipHostMallocDefault));
+    *h->nact_pinned = 0;
+    HIP_TRY(h, hipEventCreateWithFlags(&h->nact_ev, hipEventDisableTiming));
+  }
+  HIP_TRY(h, hipMemcpy(D.bfrac, h->bfrac_h.data(), sizeof(float) * P.nb, hipMemcpyHostToDevice));
   // the rest slot, in both population buffers
   for (int b = 0; b < 2; ++b) {
     hipError_t e = launch_init_slots(P, D, b, P.capacity, 1, false, false, h->stream);
@@ -436,8 +462,13 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
     if ((int)sblock.size() > cap) return fail(h, LBM_ENOMEM, "pool_blocks smaller than the blocks holding fluid");
   }
   HIP_TRY(h, hipMemcpy(D.block_slot, bslot.data(), sizeof(int32_t) * P.nb, hipMemcpyHostToDevice));
-  if (!sblock.empty())
+  if (!sblock.empty()) {
     HIP_TRY(h, hipMemcpy(D.slot_block, sblock.data(), sizeof(int32_t) * sblock.size(), hipMemcpyHostToDevice));
+    // static mesh: slots were assigned in block order
+    std::vector<int32_t> ord(sblock.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int32_t)k;
+    HIP_TRY(h, hipMemcpy(D.order, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice));
+  }
   int32_t ctrl[kNumCtrl] = {0};
   ctrl[kNActive] = (int32_t)sblock.size();
   HIP_TRY(h, hipMemcpy(D.ctrl, ctrl, sizeof ctrl, hipMemcpyHostToDevice));
@@ -486,13 +517,28 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     const bool pull = h->step > 0;
     const int rb = h->rbuf;
     int rc;
-    if (h->user.progressive) {
+    if (h->user.progressive && h->nact_pending && hipEventQuery(h->nact_ev) == hipSuccess) {
+      h->nact_pending = false;
+      if (*h->nact_pinned >= h->n_fluid_blocks) h->mesh_complete = true;
+    }
+    if (h->user.progressive && !h->mesh_complete) {
       // criterion and leak checks on the frontier, then the requested blocks
       // join this step
       const int flags = h->step == 0 ? (kCritRecord | kCritExposure)
                                      : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
       rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, pull, flags, h->stream); });
       if (rc) return rc;
+      if (h->prop_enabled) {
+        // the learned proposal requests more blocks, ahead of the criterion
+        rc = timed(h, 4, [&] {
+          hipError_t e = launch_candidates(P, h->D, h->stream);
+          if (e == hipSuccess)
+            e = launch_propose(P, h->D, rb, pull, (int)h->step, h->mlp_dev, h->prop_thr, nullptr, nullptr, 0,
+                               h->stream);
+          return e;
+        });
+        if (rc) return rc;
+      }
       rc = timed(h, 1, [&] { return launch_activate(P, h->D, (int)h->step, h->stream); });
       if (rc) return rc;
       rc = timed(h, 2, [&] { return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream); });
@@ -500,6 +546,12 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     }
     rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
     if (rc) return rc;
+    if (h->user.progressive && !h->mesh_complete && !h->nact_pending && h->step % 16 == 0 && h->nact_pinned) {
+      HIP_TRY(h, hipMemcpyAsync(h->nact_pinned, h->D.ctrl + kNActive, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                h->stream));
+      HIP_TRY(h, hipEventRecord(h->nact_ev, h->stream));
+      h->nact_pending = true;
+    }
     h->rbuf ^= 1;
     h->step++;
   }
@@ -670,10 +722,44 @@ int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n) {
 
 const char* lbm_kernel_name(int32_t k) { return (k >= 0 && k < LBM_NUM_KERNELS) ? kKernelNames[k] : ""; }
 
+int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_proposal_features before lbm_set_geometry");
+  if (cap < 0 || (cap > 0 && (!feat || !block))) return fail(h, LBM_EINVAL, "bad feature buffers");
+  hipError_t e = launch_candidates(h->P, h->D, h->stream);
+  if (e == hipSuccess)
+    e = launch_propose(h->P, h->D, h->rbuf, h->step > 0, (int)h->step, nullptr, 0.0f, feat, block, cap, h->stream);
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "proposal features: %s", hipGetErrorString(e));
+  int32_t ctrl[kNumCtrl];
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(ctrl, h->D.ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+  return ctrl[kCandCount];
+}
+
+int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t enable) {
+  if (!h) return LBM_EINVAL;
+  if (!enable) {
+    h->prop_enabled = false;
+    return LBM_OK;
+  }
+  if (!params) return fail(h, LBM_EINVAL, "proposal parameters missing");
+  if (!h->user.progressive) return fail(h, LBM_EINVAL, "the proposal needs a progressive mesh");
+  if (!h->mlp_dev) {
+    h->mlp_dev = (float*)dev_alloc(h, sizeof(float) * LBM_MLP_NPARAMS);
+    if (!h->mlp_dev) return fail(h, LBM_ENOMEM, "device allocation failed (proposal)");
+  }
+  HIP_TRY(h, hipMemcpy(h->mlp_dev, params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice));
+  h->prop_thr = threshold;
+  h->prop_enabled = true;
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_t* h) {
   if (!h) return LBM_OK;
   (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->nact_ev) (void)hipEventDestroy(h->nact_ev);
+  if (h->nact_pinned) (void)hipHostFree(h->nact_pinned);
   dev_free_all(h);
   delete h;
   return LBM_OK;

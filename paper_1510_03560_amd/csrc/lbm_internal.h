@@ -27,6 +27,7 @@ enum Ctrl : int {
   kPoolFull = 3,    // set when a request did not fit the pool
   kNumeric = 4,     // set when a density was non-positive or non-finite
   kTraceLen = 5,    // activation trace entries written
+  kCandCount = 6,   // proposal candidates listed by the last k_candidates
   kNumCtrl = 8
 };
 
@@ -67,10 +68,14 @@ struct Buffers {
   float* uprev;           // [ncomp*3 planes] velocity of the previous step (criterion; progressive only)
   int32_t* block_slot;    // [nb] slot of a block, -1 when inactive
   int32_t* slot_block;    // [capacity] block of a slot (the active list)
+  int32_t* order;         // [capacity] the active slots in block order (scheduling order of the step)
   uint8_t* bfluid;        // [nb] block holds a non-solid cell
   uint8_t* solid;         // [nx*ny*nz] solid flags of the whole lattice
   int32_t* request;       // [nb] activation requests
   int32_t* expose;        // [nb] links that showed a non-rest psi to the block this step
+  int32_t* act_step;      // [nb] step at which the block was last activated, -1 never
+  float* bfrac;           // [nb] fraction of the block's cells that are fluid
+  int32_t* cand;          // [nb] proposal candidates (inactive, fluid, an active neighbour), block order
   int32_t* ctrl;          // [kNumCtrl]
   unsigned long long* counters;  // [0] leak, [1] clamps
   int32_t* trace;         // [trace_cap][2] (step, block)
@@ -98,6 +103,13 @@ enum : int {
 };
 hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
                             hipStream_t stream);
+// Learned activation proposal: list the candidate blocks, then per candidate
+// gather its 12 features; with mlp != nullptr also run the network and request
+// the block when its probability exceeds thr, else write feat[cap][12] and
+// block[cap] for the first cap candidates.
+hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream);
+hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+                          float thr, float* feat, int32_t* block, int cap, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
                          float* umix, hipStream_t stream);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,

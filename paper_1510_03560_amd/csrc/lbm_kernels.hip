@@ -726,6 +726,7 @@ __global__ void __launch_bounds__(1024) k_activate(Params P, Buffers D, int step
       const int slot = base + wave_base[wave] + lane_rank;
       D.block_slot[b] = slot;
       D.slot_block[slot] = b;
+      D.act_step[b] = step;
       if (tr0 + rank < P.trace_cap) {
         D.trace[2 * (tr0 + rank)] = step;
         D.trace[2 * (tr0 + rank) + 1] = b;
@@ -733,6 +734,30 @@ __global__ void __launch_bounds__(1024) k_activate(Params P, Buffers D, int step
     }
     if (b < P.nb) D.request[b] = 0;
     base += chunk_total;
+    __syncthreads();
+  }
+  // the active slots in block order, which is the order the step kernel
+  // schedules them in (neighbouring blocks run together and share one L2)
+  int obase = 0;
+  for (int b0 = 0; b0 < P.nb; b0 += 1024) {
+    const int b = b0 + t;
+    const int sl = b < P.nb ? D.block_slot[b] : -1;
+    const int flag = sl >= 0 ? 1 : 0;
+    const unsigned long long bal = __ballot(flag);
+    const int lane_rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_count[wave] = __popcll(bal);
+    __syncthreads();
+    if (t == 0) {
+      int acc = 0;
+      for (int w = 0; w < 16; ++w) {
+        wave_base[w] = acc;
+        acc += wave_count[w];
+      }
+      chunk_total = acc;
+    }
+    __syncthreads();
+    if (flag) D.order[obase + wave_base[wave] + lane_rank] = sl;
+    obase += chunk_total;
     __syncthreads();
   }
   // failing links recorded by the criterion: leaks if their block is still
@@ -855,8 +880,9 @@ constexpr int kFoot = kH * kH;  // 324 columns
 template <typename S, int NC, bool PULL>
 __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, int rbuf) {
   const int n_active = D.ctrl[kNActive];
-  const int s = slot_of_workgroup(blockIdx.x, n_active);
-  if (s >= n_active) return;
+  const int g = slot_of_workgroup(blockIdx.x, n_active);
+  if (g >= n_active) return;
+  const int s = D.order[g];  // active slots in block order
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
   __shared__ uint32_t mask_s[2][kFusedThreads];
@@ -1191,6 +1217,206 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params P, Buffers D, int
   }
 }
 
+// -------------------------------------------------------------- proposal
+// The learned activation proposal.  k_candidates lists, in block order, the
+// inactive blocks holding fluid that have an active neighbour (one
+// workgroup, wave ballot + scan as in k_activate).
+__global__ void __launch_bounds__(1024) k_candidates(Params P, Buffers D) {
+  __shared__ int wave_count[16];
+  __shared__ int wave_base[16];
+  __shared__ int chunk_total;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int base = 0;
+  for (int b0 = 0; b0 < P.nb; b0 += 1024) {
+    const int b = b0 + t;
+    int flag = 0;
+    if (b < P.nb && D.block_slot[b] < 0 && D.bfluid[b]) {
+      const int bx = b % P.nbx, by = (b / P.nbx) % P.nby, bz = b / (P.nbx * P.nby);
+      for (int d = 0; d < 27 && !flag; ++d) {
+        if (d == 13) continue;
+        const int nb = neighbour_block(P, bx, by, bz, d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1);
+        if (nb >= 0 && D.block_slot[nb] >= 0) flag = 1;
+      }
+    }
+    const unsigned long long bal = __ballot(flag);
+    const int lane_rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_count[wave] = __popcll(bal);
+    __syncthreads();
+    if (t == 0) {
+      int acc = 0;
+      for (int w = 0; w < 16; ++w) {
+        wave_base[w] = acc;
+        acc += wave_count[w];
+      }
+      chunk_total = acc;
+    }
+    __syncthreads();
+    if (flag) D.cand[base + wave_base[wave] + lane_rank] = b;
+    base += chunk_total;
+    __syncthreads();
+  }
+  if (t == 0) D.ctrl[kCandCount] = base;
+}
+
+// One workgroup per candidate N.  For every active neighbour B of N it
+// visits the cells of B within `shell` cells of N (a slab of B), pulls them
+// as the criterion does and adds up rho_a, |u_a| and |psi_a - psi_rest,a|;
+// the sums are reduced over the threads in a fixed order.  Features (in this
+// order): the six means, the steps since a neighbour of N was activated,
+// N's fluid fraction, N's number of active neighbours, and the mean over the
+// active neighbours of the unit vector from B to N.  With mlp set the
+// workgroup then evaluates the network (the same arithmetic as
+// lbm_mlp_forward) and requests N when sigma(z) > thr.
+constexpr int kFeat = 12;
+constexpr int kPropThreads = 256;
+
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, int rbuf, int step,
+                                                          const float* __restrict__ mlp, float thr,
+                                                          float* __restrict__ feat_out,
+                                                          int32_t* __restrict__ block_out, int cap) {
+  const int ci = blockIdx.x;
+  if (ci >= D.ctrl[kCandCount]) return;
+  const int N = D.cand[ci];
+  const int t = threadIdx.x;
+  __shared__ int slot5[125];     // slots of N's neighbourhood, offsets -2..2 (-1: inactive or outside)
+  __shared__ int nslotB[27];     // the 27 neighbour slots of the block being visited
+  __shared__ float red[8][kPropThreads];
+  __shared__ float fe[kFeat];
+  __shared__ float h1s[64];
+  __shared__ float h2s[64];
+  const int bx = N % P.nbx, by = (N / P.nbx) % P.nby, bz = N / (P.nbx * P.nby);
+  if (t < 125) {
+    const int nb = neighbour_block(P, bx, by, bz, t % 5 - 2, (t / 5) % 5 - 2, t / 25 - 2);
+    slot5[t] = nb < 0 ? -1 : D.block_slot[nb];
+  }
+  __syncthreads();
+  const uint32_t plane = P.plane;
+  const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
+  const int w = P.shell;
+  float acc[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc[q] = 0.0f;
+  int n_act = 0, last_act = -1;
+  float dirx = 0.0f, diry = 0.0f, dirz = 0.0f;
+#pragma unroll 1
+  for (int d = 0; d < 27; ++d) {
+    const int ox = d % 3 - 1, oy = (d / 3) % 3 - 1, oz = d / 9 - 1;  // offset of B from N
+    if (d == 13) continue;
+    const int sB = slot5[(ox + 2) + 5 * ((oy + 2) + 5 * (oz + 2))];
+    if (sB < 0) continue;  // uniform
+    {
+      const int nbid = neighbour_block(P, bx, by, bz, ox, oy, oz);
+      n_act += 1;
+      last_act = max(last_act, D.act_step[nbid]);
+      const float inv = 1.0f / sqrtf((float)(ox * ox + oy * oy + oz * oz));
+      dirx = dirx - ox * inv;
+      diry = diry - oy * inv;
+      dirz = dirz - oz * inv;
+    }
+    __syncthreads();  // nslotB of the previous neighbour no longer in use
+    if (t < 27) {
+      const int ex = t % 3 - 1, ey = (t / 3) % 3 - 1, ez = t / 9 - 1;
+      const int sl = slot5[(ox + ex + 2) + 5 * ((oy + ey + 2) + 5 * (oz + ez + 2))];
+      nslotB[t] = sl < 0 ? P.capacity : sl;
+    }
+    __syncthreads();
+    // the slab of B within w cells of N
+    const int x0 = ox > 0 ? 0 : (ox < 0 ? kB - w : 0), lx = ox != 0 ? w : kB;
+    const int y0 = oy > 0 ? 0 : (oy < 0 ? kB - w : 0), ly = oy != 0 ? w : kB;
+    const int z0 = oz > 0 ? 0 : (oz < 0 ? kB - w : 0), lz = oz != 0 ? w : kB;
+    const int total = lx * ly * lz;
+#pragma unroll 1
+    for (int c = t; c < total; c += kPropThreads) {
+      const int x = x0 + c % lx, y = y0 + (c / lx) % ly, z = z0 + c / (lx * ly);
+      const uint32_t cid = (uint32_t)sB * kCells + (uint32_t)(x + 16 * y + 256 * z);
+      const uint32_t m = ld(D.mask, cid * 4u);
+      const uint32_t kind = (m >> kKindShift) & 3u;
+      if (kind == kSolid) continue;
+      PullAxes pa;
+      pull_axes_xy(x, y, pa);
+      pull_axes_z(z, pa);
+      Sources<S::kRef> src;
+      sources<PULL, S::kRef>(pa, cid, m, plane, nslotB, src);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        float f[kQ];
+        gather<S>(fb, plane, a, src, rref, f);
+        const Mom mo = moments(f);
+        float inv = 0.0f;
+        if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
+        const float ux = mo.jx * inv, uy = mo.jy * inv, uz = mo.jz * inv;
+        float psi = P.psi_rest[a];
+        if (kind == kFluid) {
+          bool cl;
+          psi = pseudo_potential(P, a, mo.rho, cl);
+        } else if (kind == kInlet) {
+          psi = P.psi_in[a];
+        }
+        acc[a] = acc[a] + mo.rho;
+        acc[2 + a] = acc[2 + a] + sqrtf((ux * ux + uy * uy) + uz * uz);
+        acc[4 + a] = acc[4 + a] + fabsf(psi - P.psi_rest[a]);
+      }
+      acc[6] = acc[6] + 1.0f;
+    }
+  }
+  // fixed-order reduction over the threads
+#pragma unroll
+  for (int q = 0; q < 7; ++q) red[q][t] = acc[q];
+  __syncthreads();
+  for (int h = kPropThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) red[q][t] = red[q][t] + red[q][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const float cnt = red[6][0];
+    const float icnt = cnt > 0.0f ? 1.0f / cnt : 0.0f;
+    for (int q = 0; q < 6; ++q) fe[q] = red[q][0] * icnt;
+    fe[6] = (float)(step - last_act);
+    fe[7] = D.bfrac[N];
+    fe[8] = (float)n_act;
+    const float ia = n_act > 0 ? 1.0f / (float)n_act : 0.0f;
+    fe[9] = dirx * ia;
+    fe[10] = diry * ia;
+    fe[11] = dirz * ia;
+    if (!mlp && ci < cap) {
+      for (int q = 0; q < kFeat; ++q) feat_out[(size_t)ci * kFeat + q] = fe[q];
+      block_out[ci] = N;
+    }
+  }
+  if (!mlp) return;  // uniform
+  __syncthreads();
+  // the network, with the arithmetic of lbm_mlp_forward
+  constexpr int kW1 = 2 * kFeat, kB1 = kW1 + 64 * kFeat, kW2 = kB1 + 64, kB2 = kW2 + 64 * 64, kW3 = kB2 + 64,
+                kB3 = kW3 + 64;
+  if (t < 64) {
+    float xn[kFeat];
+#pragma unroll
+    for (int i = 0; i < kFeat; ++i) xn[i] = (fe[i] - mlp[i]) * mlp[kFeat + i];
+    float a1 = mlp[kB1 + t];
+#pragma unroll
+    for (int i = 0; i < kFeat; ++i) a1 = a1 + mlp[kW1 + t * kFeat + i] * xn[i];
+    h1s[t] = a1 > 0.0f ? a1 : 0.0f;
+  }
+  __syncthreads();
+  if (t < 64) {
+    float a2 = mlp[kB2 + t];
+    for (int k = 0; k < 64; ++k) a2 = a2 + mlp[kW2 + t * 64 + k] * h1s[k];
+    h2s[t] = a2 > 0.0f ? a2 : 0.0f;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float z = mlp[kB3];
+    for (int j = 0; j < 64; ++j) z = z + mlp[kW3 + j] * h2s[j];
+    const float p = 1.0f / (1.0f + expf(-z));
+    if (p > thr) D.request[N] = 1;
+  }
+}
+
 // ---------------------------------------------------------------- export
 // Lattice-wide default: rest state for fluid cells, zeros for solid cells.
 __global__ void k_fill_default(Params P, Buffers D, float* rho, float* u, float* umix) {
@@ -1387,6 +1613,18 @@ struct CriterionL {
   }
 };
 template <typename S, int NC>
+struct ProposeL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+                           float thr, float* feat, int32_t* block, int cap, hipStream_t st) {
+    const dim3 g(P.nb > 0 ? P.nb : 1), b(kPropThreads);
+    if (pull)
+      hipLaunchKernelGGL((k_propose<S, NC, true>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
+    else
+      hipLaunchKernelGGL((k_propose<S, NC, false>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
+    return hipGetLastError();
+  }
+};
+template <typename S, int NC>
 struct ExportL {
   static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* r, float* u, float* m,
                            hipStream_t st) {
@@ -1433,6 +1671,16 @@ hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, 
 hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
                             hipStream_t stream) {
   return dispatch<CriterionL>(P, D, rbuf, pull, flags, stream);
+}
+
+hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream) {
+  hipLaunchKernelGGL(k_candidates, dim3(1), dim3(1024), 0, stream, P, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+                          float thr, float* feat, int32_t* block, int cap, hipStream_t stream) {
+  return dispatch<ProposeL>(P, D, rbuf, pull, step, mlp, thr, feat, block, cap, stream);
 }
 
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u, float* umix,

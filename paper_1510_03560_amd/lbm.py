@@ -202,7 +202,7 @@ def lbm_timing_enable(h, enable: bool):
     _check(load().lbm_timing_enable(h, int(bool(enable))), h)
 
 
-def lbm_timing_read(h, n: int = 4):
+def lbm_timing_read(h, n: int = 5):
     counts = np.zeros(n, dtype=np.int64)
     ms = np.zeros(n)
     _check(load().lbm_timing_read(h, _ptr(counts, C.c_int64), _ptr(ms, C.c_double), n), h)

@@ -23,8 +23,11 @@ def L():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(lbm_\w+)\(", text, re.M)))
+    import glob
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        names |= set(re.findall(r"^(?:int|const char\*)\s+(lbm_\w+)\(", open(h).read(), re.M))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(L):
@@ -34,6 +37,10 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(lib, n), n
     assert set(L.EXPORTS) <= set(names)
+    from paper_1510_03560_amd import mlp
+    assert set(mlp.EXPORTS) <= set(names)
+    assert {"lbm_mlp_forward", "lbm_mlp_backward", "lbm_mlp_adam", "lbm_proposal_features",
+            "lbm_set_proposal"} <= set(names)
 
 
 def test_struct_layout_matches_header(L, tmp_path):
