@@ -221,6 +221,88 @@ def run_channels(args):
     print(json.dumps(res), flush=True)
 
 
+def batch_cases(args):
+    """Many small progressive porous-injection runs: lattice sides drawn from
+    32..128 in steps of 16, porosity uniform in [0.5, 0.8], one seed each."""
+    from paper_1510_03560_amd import workloads as W
+    rng = np.random.Generator(np.random.PCG64(args.seed))
+    cases = []
+    for k in range(args.batch_sims):
+        shape = tuple(int(v) for v in 16 * rng.integers(2, 9, size=3))
+        cases.append(W.porous_injection(0, seed=1000 + k, porosity=float(rng.uniform(0.5, 0.8)), shape=shape))
+    return cases
+
+
+def run_batch(args):
+    """Batched stepping: the same set of small simulations advanced (a) one
+    handle after another with lbm_step, (b) as one batch launching each step
+    eagerly, (c) as one batch replaying captured graphs.  Time is wall clock
+    between device-wide synchronisations (the batch runs on its own stream);
+    final states are compared bit for bit through the mass and counters."""
+    import torch
+    from paper_1510_03560_amd import batch, lbm
+
+    torch.cuda.set_device(0)
+    cases = batch_cases(args)
+    K, Wm = args.steps, args.warmup
+    print(f"bench: batch of {len(cases)} cases generated, {sum(c.N for c in cases) / 1e6:.2f} M cells",
+          file=sys.stderr, flush=True)
+    out = {}
+    for mode in ("alone", "batch_eager", "batch_graph"):
+        sims = [lbm.Simulation(c) for c in cases]
+        b = batch.Batch(sims) if mode != "alone" else None
+
+        def advance(n):
+            if b is None:
+                for s_ in sims:
+                    s_.step(n)
+            else:
+                b.step(n, use_graph=(mode == "batch_graph"))
+
+        advance(Wm)
+        torch.cuda.synchronize()
+        n0 = [s_.stats()["n_active"] for s_ in sims]
+        tr0 = [len(s_.trace()) for s_ in sims]
+        t0 = time.perf_counter()
+        advance(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cells = 0
+        finals = []
+        for s_, a, l0 in zip(sims, n0, tr0):
+            new = s_.trace()[l0:]
+            cells += 4096 * int(active_cells_per_step(new, a, Wm, K).sum())
+            st = s_.stats()
+            finals.append((st["n_active"], st["activations"], st["leak"], tuple(st["mass"])))
+        if b is not None:
+            b.close()
+        for s_ in sims:
+            s_.close()
+        out[mode] = dict(wall=wall, cells=cells, finals=finals)
+        print(f"bench: batch mode {mode}: {K} steps in {wall * 1e3:.1f} ms, "
+              f"{cells / wall / 1e6:.1f} active-cell MLUPS", file=sys.stderr, flush=True)
+    g = out["batch_graph"]
+    res = {
+        "metric": "active-cell MLUPS",
+        "value": round(g["cells"] / g["wall"] / 1e6, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": round(g["wall"] * 1e3 / K, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(cases)} progressive porous-injection runs, sides 32-128, "
+                               f"porosity 0.5-0.8, FP32, graph replay",
+                   "shapes": [[c.params["nx"], c.params["ny"], c.params["nz"]] for c in cases],
+                   "seed": args.seed},
+        "alone_ms_per_step": round(out["alone"]["wall"] * 1e3 / K, 4),
+        "batch_eager_ms_per_step": round(out["batch_eager"]["wall"] * 1e3 / K, 4),
+        "speedup_graph_over_alone": round(out["alone"]["wall"] / g["wall"], 3),
+        "identical_to_alone": bool(all(out[m]["finals"] == out["alone"]["finals"]
+                                       for m in ("batch_eager", "batch_graph"))),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def run_proposal(args):
     """The learned activation proposal: training data from criterion-only
     progressive runs (porous injection at 128^3, seeds 0..n_train-1), the
@@ -328,7 +410,7 @@ def main():
                     help="print the step kernel's HBM bytes per launch from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--last", type=int, default=20,
                     help="with --summarize-*: number of final step-kernel launches to use (full mesh)")
-    ap.add_argument("--workload", choices=["porous", "channels", "proposal"], default="porous",
+    ap.add_argument("--workload", choices=["porous", "channels", "proposal", "batch"], default="porous",
                     help="porous: the 192^3 porous injection (default); channels: the channel network; "
                          "proposal: train and evaluate the learned activation proposal")
     ap.add_argument("--train-seeds", type=int, default=32)
@@ -340,6 +422,7 @@ def main():
     ap.add_argument("--channel-shape", type=int, nargs=3, default=[1024, 1024, 128])
     ap.add_argument("--channel-tubes", type=int, default=8)
     ap.add_argument("--sample-every", type=int, default=100)
+    ap.add_argument("--batch-sims", type=int, default=48)
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.last))
@@ -356,6 +439,9 @@ def main():
         return
     if args.workload == "proposal":
         run_proposal(args)
+        return
+    if args.workload == "batch":
+        run_batch(args)
         return
 
     import torch

@@ -11,7 +11,7 @@ LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_api.cpp"),
            os.path.join(CSRC, "mlp_kernels.hip")]
 HEADERS = [os.path.join(CSRC, "lbm_internal.h"), os.path.join(ROOT, "include", "lbm.h"),
-           os.path.join(ROOT, "include", "lbm_mlp.h")]
+           os.path.join(ROOT, "include", "lbm_mlp.h"), os.path.join(ROOT, "include", "lbm_batch.h")]
 
 # No floating-point contraction: the same expression must round the same way
 # in every kernel (the rest state is a bitwise fixed point of the update).

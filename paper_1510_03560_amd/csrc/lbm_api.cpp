@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_batch.h"
 #include "lbm_internal.h"
 #include "lbm_mlp.h"
 
@@ -500,18 +501,29 @@ int lbm_activate(lbm_t* h, const int32_t* ids, int32_t n) {
   return sync(h);
 }
 
+namespace {
+// A progressive run starts from blocks the caller activated: every block with
+// inlet nodes must be among them (the criterion only looks at active blocks).
+int check_inlet_blocks(lbm_t* h) {
+  const Params& P = h->P;
+  std::vector<int32_t> bslot(P.nb);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(bslot.data(), h->D.block_slot, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost));
+  for (int b = 0; b < P.nb; ++b)
+    if (h->binlet_h[b] && bslot[b] < 0)
+      return fail(h, LBM_EINVAL, "block %d holds inlet nodes but is not active at t = 0", b);
+  return LBM_OK;
+}
+}  // namespace
+
 int lbm_step(lbm_t* h, int32_t nsteps) {
   if (!h) return LBM_EINVAL;
   if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_step before lbm_set_geometry");
   if (nsteps < 0) return fail(h, LBM_EINVAL, "nsteps < 0");
   const Params& P = h->P;
   if (h->step == 0 && nsteps > 0 && h->user.progressive) {
-    std::vector<int32_t> bslot(P.nb);
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    HIP_TRY(h, hipMemcpy(bslot.data(), h->D.block_slot, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost));
-    for (int b = 0; b < P.nb; ++b)
-      if (h->binlet_h[b] && bslot[b] < 0)
-        return fail(h, LBM_EINVAL, "block %d holds inlet nodes but is not active at t = 0", b);
+    const int rc = check_inlet_blocks(h);
+    if (rc) return rc;
   }
   for (int32_t k = 0; k < nsteps; ++k) {
     const bool pull = h->step > 0;
@@ -751,6 +763,140 @@ int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t ena
   HIP_TRY(h, hipMemcpy(h->mlp_dev, params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice));
   h->prop_thr = threshold;
   h->prop_enabled = true;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batch
+struct lbm_batch {
+  std::vector<lbm_t*> members;
+  hipStream_t stream = nullptr;  // own stream: graphs cannot be captured on the null stream
+  hipEvent_t done = nullptr;
+  Batch B{};
+  Params* P_dev = nullptr;
+  Buffers* D_dev = nullptr;
+  int32_t* off_dev = nullptr;
+  bool progressive = false;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
+};
+
+namespace {
+int batch_fail(const char* what, hipError_t e) {
+  g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+}  // namespace
+
+int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
+  if (!hs || n < 1 || !out) return fail(nullptr, LBM_EINVAL, "batch: NULL argument or n < 1");
+  *out = nullptr;
+  lbm_t* h0 = hs[0];
+  for (int i = 0; i < n; ++i) {
+    lbm_t* h = hs[i];
+    if (!h) return fail(nullptr, LBM_EINVAL, "batch: member %d is NULL", i);
+    if (!h->geometry) return fail(nullptr, LBM_ESTATE, "batch: member %d has no geometry", i);
+    if (h->P.store != h0->P.store || h->P.ncomp != h0->P.ncomp || h->user.progressive != h0->user.progressive)
+      return fail(nullptr, LBM_EINVAL, "batch: member %d differs in store, ncomp or mesh mode", i);
+    if (h->step != h0->step || h->rbuf != h0->rbuf)
+      return fail(nullptr, LBM_EINVAL, "batch: member %d is at another step", i);
+    if (h->prop_enabled) return fail(nullptr, LBM_EINVAL, "batch: member %d has the proposal enabled", i);
+  }
+  lbm_batch* b = new lbm_batch();
+  b->members.assign(hs, hs + n);
+  b->progressive = h0->user.progressive != 0;
+  std::vector<Params> P(n);
+  std::vector<Buffers> D(n);
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    P[i] = hs[i]->P;
+    D[i] = hs[i]->D;
+    total += hs[i]->P.capacity;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->P_dev, sizeof(Params) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->D_dev, sizeof(Buffers) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->off_dev, sizeof(int32_t) * (n + 1));
+  if (e == hipSuccess) e = hipMemcpy(b->P_dev, P.data(), sizeof(Params) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->D_dev, D.data(), sizeof(Buffers) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    lbm_batch_destroy(b);
+    return batch_fail("batch create", e);
+  }
+  b->B = Batch{b->P_dev, b->D_dev, b->off_dev, n, total};
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  if (nsteps == 0) return LBM_OK;
+  lbm_t* h0 = b->members[0];
+  for (lbm_t* h : b->members)
+    if (h->step != h0->step || h->rbuf != h0->rbuf) return LBM_ESTATE;
+  const Params& P0 = h0->P;
+  if (h0->step == 0 && b->progressive)
+    for (lbm_t* h : b->members) {
+      const int rc = check_inlet_blocks(h);
+      if (rc) return rc;
+    }
+  // order after the members' queued work; the device step counters follow
+  // the members' step counts
+  for (lbm_t* h : b->members) {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int32_t st = (int32_t)h->step;
+    HIP_TRY(h, hipMemcpy(h->D.ctrl + kStepCount, &st, sizeof st, hipMemcpyHostToDevice));
+  }
+  hipError_t e = launch_batch_offsets(b->B, P0, b->stream);
+  int64_t step = h0->step;
+  int rbuf = h0->rbuf;
+  int32_t k = 0;
+  auto eager = [&](bool first) {
+    hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->stream);
+    rbuf ^= 1;
+    step++;
+    k++;
+    return r;
+  };
+  if (e == hipSuccess && step == 0) e = eager(true);
+  while (e == hipSuccess && k + 2 <= nsteps && use_graph) {
+    hipGraphExec_t& g = b->graph[rbuf];
+    if (!g) {
+      hipGraph_t graph = nullptr;
+      e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->stream);
+      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->stream);
+      hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+      if (e == hipSuccess) e = ec;
+      if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) break;
+    }
+    e = hipGraphLaunch(g, b->stream);
+    step += 2;
+    k += 2;
+  }
+  while (e == hipSuccess && k < nsteps) e = eager(false);
+  if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
+  for (lbm_t* h : b->members) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, b->done, 0);
+    h->step += nsteps;
+    h->rbuf ^= (nsteps & 1);
+  }
+  if (e != hipSuccess) return fail(h0, LBM_EHIP, "batch step: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch_t* b) {
+  if (!b) return LBM_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (hipGraphExec_t g : b->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (b->P_dev) (void)hipFree(b->P_dev);
+  if (b->D_dev) (void)hipFree(b->D_dev);
+  if (b->off_dev) (void)hipFree(b->off_dev);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
   return LBM_OK;
 }
 

@@ -28,6 +28,7 @@ enum Ctrl : int {
   kNumeric = 4,     // set when a density was non-positive or non-finite
   kTraceLen = 5,    // activation trace entries written
   kCandCount = 6,   // proposal candidates listed by the last k_candidates
+  kStepCount = 7,   // steps taken (maintained on the device by batched stepping)
   kNumCtrl = 8
 };
 
@@ -83,6 +84,17 @@ struct Buffers {
   const float* init_u;    // [3][N] initial velocity, or null
 };
 
+// Batched stepping: several simulations advanced by the same launches.  P
+// and D are device tables (one entry per simulation); off[nsims + 1] holds
+// the prefix sums of their active block counts (the merged active list).
+struct Batch {
+  const Params* P;
+  const Buffers* D;
+  int32_t* off;
+  int32_t nsims;
+  int32_t total_capacity;
+};
+
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the
 // launch status.
 // Rest state: bg = device [2] background densities; out = device
@@ -110,6 +122,13 @@ hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pu
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream);
 hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
                           float thr, float* feat, int32_t* block, int cap, hipStream_t stream);
+// Batched step: criterion (progressive), activation, initialisation,
+// merged list, fused step, step counters; `first` selects the first step
+// of a run (populations read in place).  Every member must share store,
+// component count, mode and step parity.
+hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream);
+hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
+                             hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
                          float* umix, hipStream_t stream);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,

@@ -482,6 +482,20 @@ __device__ __forceinline__ int slot_of_workgroup(int g, int n_active) {
 }
 __host__ __device__ constexpr int grid_for(int capacity) { return (capacity + kXcds - 1) / kXcds * kXcds; }
 
+// Simulation of position gi of a batch's merged active list: the last i with
+// off[i] <= gi (members without active blocks have off[i] == off[i + 1]).
+__device__ __forceinline__ int batch_sim(const Batch& B, int gi) {
+  int lo = 0, hi = B.nsims - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B.off[mid] <= gi)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename S>
 __device__ __forceinline__ typename S::T* fplane(const Buffers& D, int buf) {
   return reinterpret_cast<typename S::T*>(D.f[buf]);
@@ -566,8 +580,12 @@ __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) 
 // criterion history.  Slot `capacity` (the rest slot) is initialised the same
 // way with the rest state everywhere and an all-fluid mask.
 template <typename S>
-__global__ void __launch_bounds__(256) k_init(Params P, Buffers D, int buf, int first_h, int count_h, int from_dev,
-                                              int use_init) {
+__global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, int first_h, int count_h, int from_dev,
+                                              int use_init, Batch Bt) {
+  // batched: blockIdx.y selects the simulation
+  const bool batched = Bt.nsims > 0;
+  const Params& P = batched ? Bt.P[blockIdx.y] : Pv;
+  const Buffers& D = batched ? Bt.D[blockIdx.y] : Dv;
   const int first = from_dev ? D.ctrl[kNewFirst] : first_h;
   const int count = from_dev ? D.ctrl[kNewCount] : count_h;
   const uint32_t plane = P.plane;
@@ -691,7 +709,12 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
 // K3: one workgroup of 1024 threads compacts the requested blocks (inactive,
 // holding fluid) into new slots, in block order: slot = n_active + rank, with
 // the rank from a wave ballot and a workgroup prefix sum.  Clears requests.
-__global__ void __launch_bounds__(1024) k_activate(Params P, Buffers D, int step) {
+template <bool BATCH>
+__global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int step_arg, Batch Bt) {
+  // batched: one workgroup per simulation, whose step count is on the device
+  const Params& P = BATCH ? Bt.P[blockIdx.x] : Pv;
+  const Buffers& D = BATCH ? Bt.D[blockIdx.x] : Dv;
+  const int step = BATCH ? D.ctrl[kStepCount] : step_arg;
   __shared__ int wave_count[16];
   __shared__ int wave_base[16];
   __shared__ int chunk_total;
@@ -877,11 +900,23 @@ constexpr int kFusedThreads = 384;
 constexpr int kPsiRing = 4;
 constexpr int kFoot = kH * kH;  // 324 columns
 
-template <typename S, int NC, bool PULL>
-__global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, int rbuf) {
-  const int n_active = D.ctrl[kNActive];
-  const int g = slot_of_workgroup(blockIdx.x, n_active);
-  if (g >= n_active) return;
+template <typename S, int NC, bool PULL, bool BATCH>
+__global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, int rbuf, Batch Bt) {
+  int sim = 0, g;
+  if constexpr (BATCH) {
+    const int total = Bt.off[Bt.nsims];
+    const int gi = slot_of_workgroup(blockIdx.x, total);
+    if (gi >= total) return;
+    sim = batch_sim(Bt, gi);
+    g = gi - Bt.off[sim];
+  }
+  const Params& P = BATCH ? Bt.P[sim] : Pv;
+  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  if constexpr (!BATCH) {
+    const int n_active = D.ctrl[kNActive];
+    g = slot_of_workgroup(blockIdx.x, n_active);
+    if (g >= n_active) return;
+  }
   const int s = D.order[g];  // active slots in block order
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
@@ -1087,11 +1122,23 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params P, Buffers D, in
 // The shell cells of a block are first compacted into an LDS list (in any
 // order: every result is a per-cell store, an integer atomic or a bit OR), so
 // that all threads work on them together.
-template <typename S, int NC, bool PULL>
-__global__ void __launch_bounds__(kThreads) k_criterion(Params P, Buffers D, int rbuf, int flags) {
-  const int n_active = D.ctrl[kNActive];
-  const int s = slot_of_workgroup(blockIdx.x, n_active);
-  if (s >= n_active) return;
+template <typename S, int NC, bool PULL, bool BATCH>
+__global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, int rbuf, int flags, Batch Bt) {
+  int sim = 0, s;
+  if constexpr (BATCH) {
+    const int total = Bt.off[Bt.nsims];
+    const int gi = slot_of_workgroup(blockIdx.x, total);
+    if (gi >= total) return;
+    sim = batch_sim(Bt, gi);
+    s = gi - Bt.off[sim];
+  }
+  const Params& P = BATCH ? Bt.P[sim] : Pv;
+  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  if constexpr (!BATCH) {
+    const int n_active = D.ctrl[kNActive];
+    s = slot_of_workgroup(blockIdx.x, n_active);
+    if (s >= n_active) return;
+  }
   __shared__ BlockCtx ctx;
   __shared__ int expo[27];
   __shared__ uint16_t list[kCells];
@@ -1571,7 +1618,7 @@ struct InitL {
                            bool use_init, hipStream_t st) {
     const int grid = from_dev ? 512 : (count > 0 ? (count < 4096 ? count : 4096) : 1);
     hipLaunchKernelGGL((k_init<S>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
-                       use_init ? 1 : 0);
+                       use_init ? 1 : 0, Batch{});
     return hipGetLastError();
   }
 };
@@ -1595,9 +1642,9 @@ struct FusedL {
   static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kFusedThreads);
     if (pull)
-      hipLaunchKernelGGL((k_fused<S, NC, true>), g, b, 0, st, P, D, rbuf);
+      hipLaunchKernelGGL((k_fused<S, NC, true, false>), g, b, 0, st, P, D, rbuf, Batch{});
     else
-      hipLaunchKernelGGL((k_fused<S, NC, false>), g, b, 0, st, P, D, rbuf);
+      hipLaunchKernelGGL((k_fused<S, NC, false, false>), g, b, 0, st, P, D, rbuf, Batch{});
     return hipGetLastError();
   }
 };
@@ -1606,9 +1653,9 @@ struct CriterionL {
   static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int flags, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kThreads);
     if (pull)
-      hipLaunchKernelGGL((k_criterion<S, NC, true>), g, b, 0, st, P, D, rbuf, flags);
+      hipLaunchKernelGGL((k_criterion<S, NC, true, false>), g, b, 0, st, P, D, rbuf, flags, Batch{});
     else
-      hipLaunchKernelGGL((k_criterion<S, NC, false>), g, b, 0, st, P, D, rbuf, flags);
+      hipLaunchKernelGGL((k_criterion<S, NC, false, false>), g, b, 0, st, P, D, rbuf, flags, Batch{});
     return hipGetLastError();
   }
 };
@@ -1621,6 +1668,45 @@ struct ProposeL {
       hipLaunchKernelGGL((k_propose<S, NC, true>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
     else
       hipLaunchKernelGGL((k_propose<S, NC, false>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
+    return hipGetLastError();
+  }
+};
+// Batched stepping: prefix sums of the members' active counts (the merged
+// active list), and the members' step counters.
+__global__ void k_batch_offsets(Batch B) {
+  if (threadIdx.x != 0) return;
+  int acc = 0;
+  B.off[0] = 0;
+  for (int i = 0; i < B.nsims; ++i) {
+    acc += B.D[i].ctrl[kNActive];
+    B.off[i + 1] = acc;
+  }
+}
+__global__ void k_batch_tick(Batch B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B.nsims) B.D[i].ctrl[kStepCount] += 1;
+}
+template <typename S, int NC>
+struct BatchL {
+  static hipError_t launch(const Params& P0, const Batch& B, int rbuf, bool first, bool progressive,
+                           hipStream_t st) {
+    const dim3 gc(grid_for(B.total_capacity)), bc(kThreads), gf(grid_for(B.total_capacity)), bf(kFusedThreads);
+    if (progressive) {
+      const int flags = first ? (kCritRecord | kCritExposure)
+                              : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
+      if (first)
+        hipLaunchKernelGGL((k_criterion<S, NC, false, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
+      else
+        hipLaunchKernelGGL((k_criterion<S, NC, true, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
+      hipLaunchKernelGGL((k_activate<true>), dim3(B.nsims), dim3(1024), 0, st, P0, Buffers{}, 0, B);
+      hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B);
+      hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
+    }
+    if (first)
+      hipLaunchKernelGGL((k_fused<S, NC, false, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B);
+    else
+      hipLaunchKernelGGL((k_fused<S, NC, true, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B);
+    hipLaunchKernelGGL(k_batch_tick, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B);
     return hipGetLastError();
   }
 };
@@ -1660,7 +1746,7 @@ hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int fir
 }
 
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream) {
-  hipLaunchKernelGGL(k_activate, dim3(1), dim3(1024), 0, stream, P, D, step);
+  hipLaunchKernelGGL((k_activate<false>), dim3(1), dim3(1024), 0, stream, P, D, step, Batch{});
   return hipGetLastError();
 }
 
@@ -1671,6 +1757,17 @@ hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, 
 hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
                             hipStream_t stream) {
   return dispatch<CriterionL>(P, D, rbuf, pull, flags, stream);
+}
+
+hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream) {
+  (void)P0;
+  hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, stream, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
+                             hipStream_t stream) {
+  return dispatch<BatchL>(P0, B, rbuf, first, progressive, stream);
 }
 
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream) {

@@ -41,6 +41,24 @@ def test_exports_every_declared_symbol(L):
     assert set(mlp.EXPORTS) <= set(names)
     assert {"lbm_mlp_forward", "lbm_mlp_backward", "lbm_mlp_adam", "lbm_proposal_features",
             "lbm_set_proposal"} <= set(names)
+    from paper_1510_03560_amd import batch
+    assert set(batch.EXPORTS) <= set(names)
+    assert {"lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy"} <= set(names)
+
+
+def test_batch_rejects_bad_arguments(L):
+    """Argument checks of lbm_batch_create / lbm_batch_step that return
+    before any device call."""
+    from paper_1510_03560_amd import batch
+    lib = batch._lib()
+    out = C.c_void_p()
+    assert lib.lbm_batch_create(None, 1, C.byref(out)) == -1
+    arr = (C.c_void_p * 1)(None)
+    assert lib.lbm_batch_create(arr, 0, C.byref(out)) == -1
+    assert lib.lbm_batch_create(arr, 1, C.byref(out)) == -1
+    assert "NULL" in L.lbm_last_error(None)
+    assert lib.lbm_batch_step(None, 1, 1) == -1
+    assert lib.lbm_batch_destroy(None) == 0
 
 
 def test_struct_layout_matches_header(L, tmp_path):

@@ -1,0 +1,116 @@
+"""Batched stepping (include/lbm_batch.h): every member of a batch must end
+bit-identical to the same simulation stepped alone with lbm_step (fields,
+activation trace, counters), whether the steps are launched one by one or
+replayed from the captured graph, and across batch calls interleaved with
+standalone steps."""
+import numpy as np
+import pytest
+
+from paper_1510_03560_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_03560_amd import lbm as L
+    L.load()
+    return L
+
+
+def progressive_cases():
+    shapes = [(32, 32, 32), (64, 48, 32), (48, 64, 64), (96, 32, 32), (32, 32, 48)]
+    return [W.porous_injection(0, seed=10 + k, porosity=0.6 + 0.04 * k, shape=s) for k, s in enumerate(shapes)]
+
+
+def static_cases():
+    return [W.porous_noise(n, seed=20 + n) for n in (32, 48, 64)]
+
+
+def snapshot(sim):
+    rho, u, umix, act = sim.moments()
+    st = sim.stats()
+    return dict(rho=rho, u=u, act=act, trace=sim.trace(),
+                counters={k: st[k] for k in ("steps", "n_active", "leak", "activations", "clamps", "numeric_error",
+                                             "pool_full")})
+
+
+def assert_same(a, b, tag):
+    for k in ("rho", "u", "act"):
+        assert np.array_equal(a[k], b[k]), f"{tag}: {k} differs"
+    assert np.array_equal(a["trace"], b["trace"]), f"{tag}: trace differs"
+    assert a["counters"] == b["counters"], f"{tag}: {a['counters']} != {b['counters']}"
+
+
+def run_alone(lbm, cases, schedule, store):
+    out = []
+    for c in cases:
+        sim = lbm.Simulation(c, store=store)
+        for kind, n in schedule:
+            sim.step(n)
+        out.append(snapshot(sim))
+        sim.close()
+    return out
+
+
+def run_batched(lbm, cases, schedule, store, use_graph):
+    from paper_1510_03560_amd import batch
+    sims = [lbm.Simulation(c, store=store) for c in cases]
+    b = batch.Batch(sims)
+    for kind, n in schedule:
+        if kind == "batch":
+            b.step(n, use_graph=use_graph)
+        else:
+            for s in sims:
+                s.step(n)
+    out = [snapshot(s) for s in sims]
+    b.close()
+    for s in sims:
+        s.close()
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_progressive_matches_alone(lbm, use_graph):
+    cases = progressive_cases()
+    schedule = [("batch", 31), ("alone", 3), ("batch", 26)]
+    ref = run_alone(lbm, cases, schedule, lbm.STORE_F32)
+    got = run_batched(lbm, cases, schedule, lbm.STORE_F32, use_graph)
+    for c, a, b in zip(cases, got, ref):
+        assert a["counters"]["activations"] > 0
+        assert_same(a, b, c.name)
+
+
+def test_batch_static_matches_alone(lbm):
+    cases = static_cases()
+    schedule = [("batch", 20), ("alone", 1), ("batch", 9)]
+    ref = run_alone(lbm, cases, schedule, lbm.STORE_F32)
+    got = run_batched(lbm, cases, schedule, lbm.STORE_F32, True)
+    for c, a, b in zip(cases, got, ref):
+        assert_same(a, b, c.name)
+
+
+def test_batch_f16_matches_alone(lbm):
+    cases = progressive_cases()[:3]
+    schedule = [("batch", 40)]
+    ref = run_alone(lbm, cases, schedule, lbm.STORE_F16DEV)
+    got = run_batched(lbm, cases, schedule, lbm.STORE_F16DEV, True)
+    for c, a, b in zip(cases, got, ref):
+        assert_same(a, b, c.name)
+
+
+def test_batch_rejects_mixed_members(lbm):
+    from paper_1510_03560_amd import batch
+    a = lbm.Simulation(progressive_cases()[0])
+    s = lbm.Simulation(static_cases()[0])
+    with pytest.raises(lbm.LbmError):
+        batch.Batch([a, s])
+    a2 = lbm.Simulation(progressive_cases()[1])
+    a2.step(1)
+    with pytest.raises(lbm.LbmError):
+        batch.Batch([a, a2])
+    for x in (a, s, a2):
+        x.close()
