@@ -64,7 +64,7 @@ def measured_traffic():
     return d.get("fused_step_bytes_per_launch")
 
 
-STEP_KERNEL = "k_fused<lbm::(anonymous namespace)::StoreF32, 2, true>"
+STEP_KERNEL = "k_fused<lbm::(anonymous namespace)::StoreF32, 2, true, false>"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 
@@ -513,6 +513,19 @@ def main():
     k2_bytes = fluid_full * per_fluid + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
 
+    # achievable HBM rate on this device: a plain 1 GiB device-to-device copy
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
     cells_p = int(prog["active_blocks_per_step"].sum()) * 4096
     value = cells_p / (prog["ms"] * 1e-3) / 1e6
     domain_cells = case.N * K
@@ -555,6 +568,8 @@ def main():
             "traffic": measured_traffic() if (n == 192 and args.store == "f32") else None,
             "bytes_per_launch": int(k2_bytes),
             "launch_ms": round(k2_ms, 5),
+            "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
     if not args.no_cpu:

@@ -107,6 +107,17 @@ __device__ __forceinline__ void st(T* base, uint32_t byte_off, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Streaming store: the populations written by a step are read back only in
+// the next step, so they should not displace the lines the current step
+// still reads from the L2 (the non-temporal hint).
+__device__ __forceinline__ void st_stream(float* base, uint32_t off, float v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off));
+}
+__device__ __forceinline__ void st_stream(__half* base, uint32_t off, __half v) {
+  __builtin_nontemporal_store(__half_as_ushort(v),
+                              reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(base) + off));
+}
+
 // --------------------------------------------------------- storage codecs
 struct StoreF32 {
   using T = float;
@@ -979,7 +990,9 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
     const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
     return ld(D.mask, ((uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15)) * 4u);
   };
-  auto in_mesh = [&](int z) { return col && ctx.nslot[dxy + 9 * sgn_out(z)] != P.capacity; };
+  // (threads without a column hand over a mask too, which they never read:
+  // the select then needs no branch, and the load is consumed on every path)
+  auto in_mesh = [&](int z) { return ctx.nslot[dxy + 9 * sgn_out(z)] != P.capacity; };
   constexpr uint32_t kNoCell = (uint32_t)kSolid << kKindShift;
   {
     const uint32_t raw = mask_load(-1);
@@ -1043,6 +1056,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
       const int zc = z - 1;
       const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * zc);
       const uint32_t kind = (mp >> kKindShift) & 3u;
+      float rr[NC];  // FP16 reference: the cell's density of this step
       if (kind == kFluid) {
         const int sl[3] = {(k + 2) % kPsiRing, (k + 3) % kPsiRing, k % kPsiRing};  // planes zc-1, zc, zc+1
         float psi_c[NC];
@@ -1056,33 +1070,36 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
                                  return solid_nb ? psi_c[a] : psi_s[sl[1 + dir_ez(i)]][a][hn];
                                },
                                F);
+        // post-collision populations replace the pulled ones (each opposite
+        // pair is read before it is written)
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-          Mom mo = moments(fp[a]);
-          const float rr = rp[a];  // FP16 reference: this cell's density of this step
-          if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
-          collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho), [&](auto I, float v) {
-            constexpr int i = decltype(I)::value;
-            constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-            constexpr bool second = i != 0 && !(i & 1);
-            const typename S::T enc = S::encode(v, dir_w(i) * rr);
-            st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-          });
+          const Mom mo = moments(fp[a]);
+          rr[a] = rp[a];
+          collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho),
+                       [&](auto I, float v) { fp[a][decltype(I)::value] = v; });
         }
       } else {
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
           // FP16 reference: a boundary node's own density of this step
-          const float rr = kind == kSolid ? P.rho_ref_rest[a] : rp[a];
-          if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr);
-          unroll<kQ>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-            constexpr bool second = i != 0 && !(i & 1);
-            const typename S::T enc = S::encode(kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i], dir_w(i) * rr);
-            st(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-          });
+          rr[a] = kind == kSolid ? P.rho_ref_rest[a] : rp[a];
+#pragma unroll
+          for (int i = 0; i < kQ; ++i) fp[a][i] = kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i];
         }
+      }
+      // one store per population for the whole wave, fluid and boundary
+      // lanes alike, so that each written line is complete in one request
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
+        unroll<kQ>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+          constexpr bool second = i != 0 && !(i & 1);
+          const typename S::T enc = S::encode(fp[a][i], dir_w(i) * rr[a]);
+          st_stream(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+        });
       }
     }
     // ---- keep plane z for its store at the next iteration
