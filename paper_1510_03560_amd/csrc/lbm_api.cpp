@@ -495,6 +495,8 @@ int lbm_activate(lbm_t* h, const int32_t* ids, int32_t n) {
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (int k = 0; k < n; ++k) req[ids[k]] = 1;
   HIP_TRY(h, hipMemcpy(h->D.request, req.data(), sizeof(int32_t) * h->P.nb, hipMemcpyHostToDevice));
+  const int32_t pending = 1;
+  HIP_TRY(h, hipMemcpy(h->D.ctrl + kPending, &pending, sizeof pending, hipMemcpyHostToDevice));
   hipError_t e = launch_activate(h->P, h->D, (int)h->step, h->stream);
   if (e == hipSuccess) e = launch_init_slots(h->P, h->D, h->rbuf, 0, 0, true, h->step == 0, h->stream);
   if (e != hipSuccess) return fail(h, LBM_EHIP, "activation: %s", hipGetErrorString(e));

@@ -29,7 +29,8 @@ enum Ctrl : int {
   kTraceLen = 5,    // activation trace entries written
   kCandCount = 6,   // proposal candidates listed by the last k_candidates
   kStepCount = 7,   // steps taken (maintained on the device by batched stepping)
-  kNumCtrl = 8
+  kPending = 8,     // requests or failing links recorded since the last activation pass
+  kNumCtrl = 9
 };
 
 // Constants of one run, passed by value to every kernel.

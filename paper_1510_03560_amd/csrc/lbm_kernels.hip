@@ -720,6 +720,8 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
 // K3: one workgroup of 1024 threads compacts the requested blocks (inactive,
 // holding fluid) into new slots, in block order: slot = n_active + rank, with
 // the rank from a wave ballot and a workgroup prefix sum.  Clears requests.
+// When the criterion (or the proposal) recorded nothing since the last pass,
+// the active set is unchanged and the pass only reports that no block is new.
 template <bool BATCH>
 __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int step_arg, Batch Bt) {
   // batched: one workgroup per simulation, whose step count is on the device
@@ -733,6 +735,13 @@ __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int st
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int n0 = D.ctrl[kNActive];
   const int tr0 = D.ctrl[kTraceLen];
+  if (D.ctrl[kPending] == 0) {  // the same value for the whole workgroup
+    if (t == 0) {
+      D.ctrl[kNewFirst] = n0;
+      D.ctrl[kNewCount] = 0;
+    }
+    return;
+  }
   int base = n0;
   if (t == 0) stop = 0;
   __syncthreads();
@@ -811,6 +820,7 @@ __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int st
     D.ctrl[kNActive] = base;
     D.ctrl[kTraceLen] = tr0 + (base - n0);
     if (stop) D.ctrl[kPoolFull] = 1;
+    D.ctrl[kPending] = stop;  // requests that did not fit stay pending
   }
 }
 
@@ -1278,6 +1288,7 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   if (t < 27) {
     if ((ctx.fired >> t) & 1u) D.request[ctx.nbk[t]] = 1;
     if (expo[t]) atomicAdd(&D.expose[ctx.nbk[t]], expo[t]);
+    if (((ctx.fired >> t) & 1u) || expo[t]) D.ctrl[kPending] = 1;
   }
 }
 
@@ -1477,7 +1488,10 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
     float z = mlp[kB3];
     for (int j = 0; j < 64; ++j) z = z + mlp[kW3 + j] * h2s[j];
     const float p = 1.0f / (1.0f + expf(-z));
-    if (p > thr) D.request[N] = 1;
+    if (p > thr) {
+      D.request[N] = 1;
+      D.ctrl[kPending] = 1;
+    }
   }
 }
 

@@ -112,5 +112,14 @@ def test_batch_rejects_mixed_members(lbm):
     a2.step(1)
     with pytest.raises(lbm.LbmError):
         batch.Batch([a, a2])
-    for x in (a, s, a2):
+    # the learned proposal runs inside lbm_step only: a member using it is refused
+    from paper_1510_03560_amd import mlp
+    a3 = lbm.Simulation(progressive_cases()[2])
+    mlp.set_proposal(a3, mlp.initial_params(0), 0.5)
+    with pytest.raises(lbm.LbmError, match="proposal"):
+        batch.Batch([a, a3])
+    mlp.set_proposal(a3, None)
+    b = batch.Batch([a, a3])
+    b.close()
+    for x in (a, s, a2, a3):
         x.close()
