@@ -329,6 +329,19 @@ __device__ __forceinline__ int neighbour_block(const Params& P, int bx, int by, 
 
 __host__ __device__ __forceinline__ int sgn_out(int s) { return s < 0 ? -1 : (s > 15 ? 1 : 0); }
 
+// Index of cell (x, y, z) within a block: x and y in tiles of 8 x 4 (one
+// 128-byte line of an FP32 population plane per tile), z planes outermost.
+// A face of the block then spans 4 (x faces) or 2 (y faces) lines of a plane
+// instead of 8 or 1, so the halo a neighbouring block reads touches fewer lines.
+__host__ __device__ constexpr uint32_t cell_x(int x) { return (uint32_t)((x & 7) + 32 * ((x >> 3) & 1)); }
+__host__ __device__ constexpr uint32_t cell_y(int y) { return (uint32_t)(8 * (y & 3) + 64 * ((y >> 2) & 3)); }
+__host__ __device__ constexpr uint32_t cell_of(int x, int y, int z) { return cell_x(x) + cell_y(y) + 256u * (uint32_t)z; }
+__host__ __device__ __forceinline__ void cell_xyz(int c, int& x, int& y, int& z) {
+  x = (c & 7) + 8 * ((c >> 5) & 1);
+  y = ((c >> 3) & 3) + 4 * ((c >> 6) & 3);
+  z = c >> 8;
+}
+
 // Sources of the 19 populations arriving at a cell.  fidx[i] is the element
 // index of the value within the two planes of direction i's opposite pair
 // (plane offset included); for the FP16 store ridx[i] is the source cell's
@@ -350,22 +363,23 @@ struct PullAxes {
   uint32_t ax[3], ay[3], az[3];
 };
 
-__host__ __device__ __forceinline__ uint32_t pack_axis(int v, int shift, int scale_d, int scale_c, int bias) {
+__host__ __device__ __forceinline__ uint32_t pack_axis(int v, int shift, int scale_d, int axis, int bias) {
   const int sv = v + shift;
   const int o = sv < 0 ? -1 : (sv > 15 ? 1 : 0);
-  return ((uint32_t)(bias + scale_d * o) << 16) + (uint32_t)(scale_c * (sv & 15));
+  const uint32_t c = axis == 0 ? cell_x(sv & 15) : (axis == 1 ? cell_y(sv & 15) : 256u * (uint32_t)(sv & 15));
+  return ((uint32_t)(bias + scale_d * o) << 16) + c;
 }
 
 __host__ __device__ __forceinline__ void pull_axes_xy(int x, int y, PullAxes& a) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    a.ax[k] = pack_axis(x, k - 1, 1, 1, 0);
-    a.ay[k] = pack_axis(y, k - 1, 3, 16, 0);
+    a.ax[k] = pack_axis(x, k - 1, 1, 0, 0);
+    a.ay[k] = pack_axis(y, k - 1, 3, 1, 0);
   }
 }
 __host__ __device__ __forceinline__ void pull_axes_z(int z, PullAxes& a) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) a.az[k] = pack_axis(z, k - 1, 9, 256, 13);
+  for (int k = 0; k < 3; ++k) a.az[k] = pack_axis(z, k - 1, 9, 2, 13);
 }
 
 template <bool PULL, bool REF>
@@ -609,7 +623,8 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
     const int bx = rest_slot ? 0 : blk % P.nbx, by = rest_slot ? 0 : (blk / P.nbx) % P.nby,
               bz = rest_slot ? 0 : blk / (P.nbx * P.nby);
     for (int c = threadIdx.x; c < kCells; c += blockDim.x) {
-      const int x = c & 15, y = (c >> 4) & 15, z = c >> 8;
+      int x, y, z;
+      cell_xyz(c, x, y, z);
       const uint32_t cid = (uint32_t)slot * kCells + c;
       uint32_t m = 0u;
       long long n = -1;
@@ -684,7 +699,8 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
   __shared__ BlockCtx ctx;
   setup_block(P, D, D.slot_block[s], ctx);
   __syncthreads();
-  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  int x, y, z0;
+  cell_xyz((int)threadIdx.x, x, y, z0);
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const uint32_t plane = P.plane;
@@ -693,7 +709,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
   const uint32_t own_base = (uint32_t)s * kCells;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
-    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t cid = own_base + cell_of(x, y, z);
     const uint32_t m = ld(D.mask, cid * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
     if (kind == kSolid) continue;
@@ -850,13 +866,14 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
     const int hx = h % kH - 1, hy = (h / kH) % kH - 1, hz = h / (kH * kH) - 1;
     const int d = 13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(hz);
     const int slot = ctx.nslot[d];
-    const uint32_t cid = (uint32_t)slot * kCells + (uint32_t)((hx & 15) + 16 * (hy & 15) + 256 * (hz & 15));
+    const uint32_t cid = (uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, hz & 15);
 #pragma unroll
     for (int a = 0; a < NC; ++a)
       psi_s[a * kHalo + h] = slot == P.capacity ? P.psi_rest[a] : ld(psi_slots + (size_t)a * plane, cid * 4u);
   }
   __syncthreads();
-  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  int x, y, z0;
+  cell_xyz((int)threadIdx.x, x, y, z0);
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
@@ -866,7 +883,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
   const long long N = (long long)P.nx * P.ny * P.nz;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
-    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t cid = own_base + cell_of(x, y, z);
     const uint32_t m = ld(D.mask, cid * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
     if (kind == kSolid) continue;
@@ -955,8 +972,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   const bool interior = t < 256;
   int cx, cy;
   if (interior) {
-    cx = t & 15;
-    cy = t >> 4;
+    int cz;
+    cell_xyz(t, cx, cy, cz);  // consecutive threads take consecutive cells of a plane
   } else {
     const int r = col ? t - 256 : 0;  // ring: rows y = -1, 16 (18 each), then columns x = -1, 16
     if (r < 18) {
@@ -977,7 +994,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   PullAxes pa;
   pull_axes_xy(cx, cy, pa);
   const int dxy = 13 + sgn_out(cx) + 3 * sgn_out(cy);
-  const uint32_t cxy = (uint32_t)((cx & 15) + 16 * (cy & 15));
+  const uint32_t cxy = cell_x(cx & 15) + cell_y(cy & 15);
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   typename S::T* __restrict__ fw = fplane<S>(D, rbuf ^ 1);
@@ -1064,7 +1081,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
     // their state; solid cells take the rest state, which nothing reads.
     if (store_next) {
       const int zc = z - 1;
-      const uint32_t cid = own_base + (uint32_t)(cx + 16 * cy + 256 * zc);
+      const uint32_t cid = own_base + cell_of(cx, cy, zc);
       const uint32_t kind = (mp >> kKindShift) & 3u;
       float rr[NC];  // FP16 reference: the cell's density of this step
       if (kind == kFluid) {
@@ -1177,7 +1194,9 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   const unsigned cand = ctx.cand;
   if (!cand) return;  // uniform
   for (int c = threadIdx.x; c < kCells; c += kThreads) {
-    const bool in_shell = (shell_dirs(c & 15, (c >> 4) & 15, c >> 8, P.shell) & cand) != 0u;
+    int cxx, cyy, czz;
+    cell_xyz(c, cxx, cyy, czz);
+    const bool in_shell = (shell_dirs(cxx, cyy, czz, P.shell) & cand) != 0u;
     const unsigned long long bal = __ballot(in_shell);
     const int lane = threadIdx.x & 63;
     int base = 0;
@@ -1196,7 +1215,8 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
 #pragma unroll 1
   for (int j = threadIdx.x; j < n_shell; j += kThreads) {
     const int c = list[j];
-    const int x = c & 15, y = (c >> 4) & 15, z = c >> 8;
+    int x, y, z;
+    cell_xyz(c, x, y, z);
     const unsigned dirs = shell_dirs(x, y, z, P.shell) & cand;
     const uint32_t cid = own_base + (uint32_t)c;
     const uint32_t m = ld(D.mask, cid * 4u);
@@ -1405,7 +1425,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
 #pragma unroll 1
     for (int c = t; c < total; c += kPropThreads) {
       const int x = x0 + c % lx, y = y0 + (c / lx) % ly, z = z0 + c / (lx * ly);
-      const uint32_t cid = (uint32_t)sB * kCells + (uint32_t)(x + 16 * y + 256 * z);
+      const uint32_t cid = (uint32_t)sB * kCells + cell_of(x, y, z);
       const uint32_t m = ld(D.mask, cid * 4u);
       const uint32_t kind = (m >> kKindShift) & 3u;
       if (kind == kSolid) continue;
@@ -1522,7 +1542,8 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
   const int blk = D.slot_block[s];
   setup_block(P, D, blk, ctx);
   __syncthreads();
-  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  int x, y, z0;
+  cell_xyz((int)threadIdx.x, x, y, z0);
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
@@ -1533,7 +1554,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
-    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t cid = own_base + cell_of(x, y, z);
     const uint32_t m = D.mask[cid];
     const bool sol = ((m >> kKindShift) & 3u) == kSolid;
     const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
@@ -1584,7 +1605,8 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
   __shared__ int cnt[kThreads];
   setup_block(P, D, D.slot_block[s], ctx);
   __syncthreads();
-  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15, z0 = threadIdx.x >> 8;
+  int x, y, z0;
+  cell_xyz((int)threadIdx.x, x, y, z0);
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const uint32_t plane = P.plane;
@@ -1595,7 +1617,7 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
   int nf = 0;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
-    const uint32_t cid = own_base + (uint32_t)(x + 16 * y + 256 * z);
+    const uint32_t cid = own_base + cell_of(x, y, z);
     const uint32_t m = D.mask[cid];
     if (((m >> kKindShift) & 3u) == kSolid) continue;
     ++nf;
