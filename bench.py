@@ -44,9 +44,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_porous192_traffic.json
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the kernel source with comments and blank lines removed, so
+    that editing a comment does not invalidate recorded counters."""
     import hashlib
+    import re
     src = os.path.join(ROOT, "paper_1510_03560_amd", "csrc", "lbm_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+    text = re.sub(r"//[^\n]*", "", open(src).read())
+    code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def measured_traffic():

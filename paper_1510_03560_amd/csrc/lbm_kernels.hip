@@ -5,9 +5,11 @@
 // Data layout.  The lattice is cut into 16^3 blocks; an active block owns a
 // slot of the pool.  Populations are structure-of-arrays (section 3) by
 // (component, direction) plane over the whole pool:
-//     f[buf][plane = comp*19 + dir][slot*4096 + cell],  cell = x + 16*(y + 16*z)
-// so the 64 lanes of a wave read or write four consecutive x-rows of one
-// plane: 256 contiguous bytes (FP32).  Every pull is a 32-bit element index
+//     f[buf][plane = comp*19 + dir][slot*4096 + cell],
+//     cell = (x mod 8) + 8 (y mod 4) + 32 (x div 8) + 64 (y div 4) + 256 z
+// (8 x 4 tiles of x and y, see cell_of), so the 64 lanes of a wave read or
+// write two whole tiles of one plane: 256 contiguous bytes (FP32), two cache
+// lines.  Every pull is a 32-bit element index
 // from a wave-uniform base (the first plane of the opposite-direction pair),
 // which keeps address arithmetic in single VGPRs and lets both components
 // share it.  The extra slot `capacity` holds the rest state and stands in for
@@ -923,8 +925,8 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
 // The production step kernel: moments, pseudo-potential, forces, collision
 // and streaming in one pass over the populations.  One workgroup per active
 // block.  Thread t owns a column of the block's 18 x 18 footprint (the block
-// plus a one-cell ring): t < 256 the 16 x 16 interior (four full waves,
-// coalesced rows), 256 <= t < 324 the ring.  The workgroup sweeps the planes
+// plus a one-cell ring): t < 256 the 16 x 16 interior (four full waves, each
+// on two whole tiles), 256 <= t < 324 the ring.  The workgroup sweeps the planes
 // z = -1 .. 16.  At plane z every column pulls its cell's populations,
 // computes rho and psi (Eq 4-7) and puts psi in a ring of four LDS planes;
 // after one barrier the interior threads collide their cell of plane z - 1
