@@ -84,6 +84,32 @@ def test_batch_progressive_matches_alone(lbm, use_graph):
         assert_same(a, b, c.name)
 
 
+def test_batch_graph_replays_match_eager(lbm):
+    """Every replay of the captured steps equals eager stepping: two batches
+    of the same members, one replaying graphs and one launching eagerly,
+    compared after each call, with standalone work and synchronisations
+    between the calls."""
+    from paper_1510_03560_amd import batch
+    cases = progressive_cases()[:3]
+    sims_g = [lbm.Simulation(c) for c in cases]
+    sims_e = [lbm.Simulation(c) for c in cases]
+    bg, be = batch.Batch(sims_g), batch.Batch(sims_e)
+    for call, n in enumerate((1, 4, 2, 6, 3, 2)):
+        bg.step(n, use_graph=True)
+        be.step(n, use_graph=False)
+        for k, (a, b) in enumerate(zip(sims_g, sims_e)):
+            ra, rb = a.moments()[0], b.moments()[0]
+            assert np.array_equal(ra, rb), f"call {call}, member {k}"
+            assert np.array_equal(a.trace(), b.trace()), f"call {call}, member {k}"
+        if call == 2:  # eager work of the members between replays
+            for x in sims_g + sims_e:
+                x.step(1)
+    bg.close()
+    be.close()
+    for x in sims_g + sims_e:
+        x.close()
+
+
 def test_batch_static_matches_alone(lbm):
     cases = static_cases()
     schedule = [("batch", 20), ("alone", 1), ("batch", 9)]
