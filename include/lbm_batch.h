@@ -37,7 +37,9 @@ int lbm_batch_create(lbm_t* const* handles, int32_t n, lbm_batch_t** out);
 /* Advances every member by nsteps steps.  use_graph = 1 replays the steps
  * from a HIP graph captured on the first call (two steps, one per buffer
  * parity); 0 launches them one by one.  Asynchronous like lbm_step.
- * Errors: LBM_EINVAL, LBM_ESTATE (members no longer at the same step), LBM_EHIP. */
+ * Errors: LBM_EINVAL, LBM_ESTATE (members no longer at the same step),
+ * LBM_EHIP (a launch or the capture failed: the members then count only the
+ * steps enqueued before the failure; the message is on the first member). */
 int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph);
 
 /* Releases the batch (not the members); waits for its work. */

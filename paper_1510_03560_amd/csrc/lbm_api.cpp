@@ -853,10 +853,12 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
   int rbuf = h0->rbuf;
   int32_t k = 0;
   auto eager = [&](bool first) {
-    hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->stream);
-    rbuf ^= 1;
-    step++;
-    k++;
+    const hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->stream);
+    if (r == hipSuccess) {
+      rbuf ^= 1;
+      step++;
+      k++;
+    }
     return r;
   };
   if (e == hipSuccess && step == 0) e = eager(true);
@@ -874,16 +876,22 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
       if (e != hipSuccess) break;
     }
     e = hipGraphLaunch(g, b->stream);
-    step += 2;
-    k += 2;
+    if (e == hipSuccess) {
+      step += 2;
+      k += 2;
+    }
   }
   while (e == hipSuccess && k < nsteps) e = eager(false);
-  if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
+  // the members advance by the steps actually enqueued (all of them unless a
+  // launch failed)
+  const hipError_t e_steps = e;
+  e = hipEventRecord(b->done, b->stream);
   for (lbm_t* h : b->members) {
     if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, b->done, 0);
-    h->step += nsteps;
-    h->rbuf ^= (nsteps & 1);
+    h->step += k;
+    h->rbuf ^= (k & 1);
   }
+  if (e_steps != hipSuccess) e = e_steps;
   if (e != hipSuccess) return fail(h0, LBM_EHIP, "batch step: %s", hipGetErrorString(e));
   return LBM_OK;
 }
