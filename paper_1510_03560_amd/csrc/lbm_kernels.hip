@@ -422,6 +422,21 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
   }
 }
 
+// As gather, with the reference density of direction i given by ref(I).
+template <typename S, typename Ref>
+__device__ __forceinline__ void gather_ref(const typename S::T* __restrict__ fb, uint32_t plane, int a,
+                                           const Sources<S::kRef>& s, Ref&& ref, float f[kQ]) {
+  using T = typename S::T;
+  constexpr uint32_t sz = sizeof(T);
+  const T* base0 = fb + (size_t)(a * kQ) * plane;
+  unroll<kQ>([&](auto K) {
+    constexpr int i = decltype(K)::value;
+    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+    const T v = ld(base0 + (size_t)first * plane, s.fidx[i] * sz);
+    f[i] = S::decode(v, dir_w(i) * ref(K));
+  });
+}
+
 // Populations of component a arriving at the cell (decoded to FP32).
 //   fb: buffer base; plane: elements per plane; rref: densities of the
 //   previous step (FP16 store only).
@@ -848,6 +863,7 @@ __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int st
 // arrays.  Psi of the 18^3 halo is staged in LDS from the first pass;
 // inactive and outside blocks show the rest value.
 constexpr int kH = kB + 2;            // halo edge
+constexpr int kRW = kB + 4;           // edge of the FP16 reference footprint
 constexpr int kHalo = kH * kH * kH;   // 5832 cells
 
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x + 1) + kH * ((y + 1) + kH * (z + 1)); }
@@ -962,6 +978,11 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   __shared__ float psi_s[kPsiRing][NC][kFoot];
   __shared__ uint32_t mask_s[2][kFusedThreads];
   __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
+  // FP16 store: the previous step's densities (the references of the stored
+  // deviations) of a 20 x 20 footprint, x and y in [-2, 17], four planes in a
+  // ring (plane p in slot p & 3), so that a pull decodes its 19 values with
+  // LDS reads instead of 19 more loads per component
+  __shared__ float rref_s[S::kRef ? kPsiRing : 1][NC][S::kRef ? kRW * kRW : 1];
   setup_block(P, D, D.slot_block[s], ctx);
   if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
     const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
@@ -1027,12 +1048,45 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
     const uint32_t raw = mask_load(-1);
     mask_s[0][t] = in_mesh(-1) ? raw : kNoCell;
   }
+  // references of plane zp: entries t, t + 384, ... of the NC x 400 values
+  constexpr int kRefPer = (NC * kRW * kRW + kFusedThreads - 1) / kFusedThreads;
+  auto rref_fetch = [&](int zp, float (&v)[kRefPer]) {
+#pragma unroll
+    for (int j = 0; j < kRefPer; ++j) {
+      const int e = t + j * kFusedThreads;
+      v[j] = 0.0f;
+      if (e < NC * kRW * kRW) {
+        const int aa = e / (kRW * kRW), col = e % (kRW * kRW);
+        const int rx = col % kRW - 2, ry = col / kRW - 2;
+        const int slot = ctx.nslot[13 + sgn_out(rx) + 3 * sgn_out(ry) + 9 * sgn_out(zp)];
+        v[j] = ld(rref + (size_t)aa * plane, ((uint32_t)slot * kCells + cell_of(rx & 15, ry & 15, zp & 15)) * 4u);
+      }
+    }
+  };
+  auto rref_put = [&](int ring, const float (&v)[kRefPer]) {
+#pragma unroll
+    for (int j = 0; j < kRefPer; ++j) {
+      const int e = t + j * kFusedThreads;
+      if (e < NC * kRW * kRW) rref_s[ring & 3][e / (kRW * kRW)][e % (kRW * kRW)] = v[j];
+    }
+  };
+  const int rcol = (cy + 2) * kRW + (cx + 2);  // this column in the reference footprint
+  if constexpr (S::kRef) {
+    for (int zp = -2; zp <= 0; ++zp) {
+      float v[kRefPer];
+      rref_fetch(zp, v);
+      rref_put(zp, v);
+    }
+    __syncthreads();
+  }
 #pragma unroll 1
   for (int k = 0; k < kH; ++k) {
     const int z = k - 1;
     const bool own = interior && z >= 0 && z < kB;
     const uint32_t m = mask_s[k & 1][t];
     const uint32_t m_ahead = mask_load(z + 1);
+    float rref_ahead[kRefPer];  // FP16: references of plane z + 2, handed over like the masks
+    if constexpr (S::kRef) rref_fetch(min(z + 2, kB + 1), rref_ahead);
     // ---- plane z: pull, moments, psi
     float f[NC][kQ];
     float rho[NC];
@@ -1053,7 +1107,21 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
           sources<PULL, S::kRef>(pa, cell, m, plane, ctx.nslot, src);
 #pragma unroll
           for (int a = 0; a < NC; ++a) {
-            gather<S>(fb, plane, a, src, rref, f[a]);
+            if constexpr (S::kRef) {
+              // references from the LDS ring: the source cell, or the cell
+              // itself for a bounced link (and on the first step, which does
+              // not stream)
+              gather_ref<S>(fb, plane, a, src,
+                            [&](auto I) {
+                              constexpr int i = decltype(I)::value;
+                              const bool self = !PULL || i == 0 || ((m >> i) & 1u);
+                              return self ? rref_s[z & 3][a][rcol]
+                                          : rref_s[(z - dir_ez(i)) & 3][a][rcol - dir_ex(i) - kRW * dir_ey(i)];
+                            },
+                            f[a]);
+            } else {
+              gather<S>(fb, plane, a, src, rref, f[a]);
+            }
             rho[a] = moments(f[a]).rho;
           }
         }
@@ -1076,6 +1144,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
       for (int a = 0; a < NC; ++a) psi_s[k % kPsiRing][a][hp] = psi[a];
     }
     mask_s[(k + 1) & 1][t] = in_mesh(z + 1) ? m_ahead : kNoCell;
+    // (past the last plane the values land in a slot no later pull reads)
+    if constexpr (S::kRef) rref_put(z + 2, rref_ahead);
     __syncthreads();
     // ---- plane z - 1: every cell of the block is stored, so that each
     // written cache line is complete (a partial line costs the memory a
