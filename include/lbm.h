@@ -151,9 +151,10 @@ int lbm_activate(lbm_t* h, const int32_t* block_ids, int32_t n);
  * pseudo-potential of every active cell, the criterion of Eq 13 on the
  * boundary shell of every active block next to an inactive block holding
  * fluid, activation of the requested blocks (they join this step's
- * collision), then forces, collision and streaming.  Asynchronous.  In
- * progressive mode every block holding an inlet node must be active before
- * the first step.  Errors: LBM_ESTATE, LBM_EINVAL (nsteps < 0, or an inlet
+ * collision), then forces, collision and streaming.  Asynchronous.  Once
+ * every block holding fluid is active the criterion has nothing left to
+ * request and the step no longer runs it.  In progressive mode every block
+ * holding an inlet node must be active before the first step.  Errors: LBM_ESTATE, LBM_EINVAL (nsteps < 0, or an inlet
  * node outside the mesh), LBM_EHIP. */
 int lbm_step(lbm_t* h, int32_t nsteps);
 
