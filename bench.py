@@ -406,7 +406,7 @@ def main():
                     help="population storage: FP32, or FP16 deviations (arithmetic is FP32 in both)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--summarize-trace", metavar="CSV",
