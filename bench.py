@@ -43,6 +43,19 @@ K2_BYTES_PER_SOLID_CELL = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_porous192_traffic.json")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name and logical CPU count (Linux)."""
+    name = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical CPUs"
+
+
 def kernel_source_hash() -> str:
     """SHA-256 of the kernel source with comments and blank lines removed, so
     that editing a comment does not invalidate recorded counters."""
@@ -400,7 +413,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=192)
     ap.add_argument("--store", choices=["f32", "f16"], default="f32",
                     help="population storage: FP32, or FP16 deviations (arithmetic is FP32 in both)")
@@ -591,7 +604,7 @@ def main():
             "cores": used,
             "kind": "oracle",
             "sample": f"{args.cpu_steps} steps of the same {n}^3 lattice on the static mesh "
-                      f"({stat['stats']['n_active']} active blocks), FP64, OpenMP",
+                      f"({stat['stats']['n_active']} active blocks), FP64, OpenMP, {cpu_model()}",
         }
     print(json.dumps(res), flush=True)
 
