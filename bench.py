@@ -449,7 +449,7 @@ def main():
         print(json.dumps(summarize_pmc(*args.summarize_pmc, args.last), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (the whole lattice lives on one MI355X); "
+        print(f"bench.py: runs on one GPU only (the whole lattice lives on one MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.workload == "channels":
