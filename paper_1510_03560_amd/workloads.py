@@ -104,6 +104,47 @@ def droplet_periodic(n: int = 32, seed: int = 0, steps: int = 200, stated: bool 
     return Case(name, params, np.zeros(N, np.uint8), rho0, np.zeros((3, N)), None, steps, dict(seed=seed))
 
 
+def droplet_seam(n: int = 48, seed: int = 0, ncomp: int = 2, steps: int = 150) -> Case:
+    """A droplet across the periodic seam, on a progressive mesh.
+
+    Fully periodic n^3 box (n a multiple of 16, at least 48).  Component 1 is
+    a sphere of radius 8 centred on the lattice corner, distances taken
+    across the periodic faces, with the tanh profile of droplet_periodic from
+    the liquid to the gas coexistence density; component 2 (if ncomp = 2) is
+    0.1.  The eight blocks around the corner are meshed at t = 0 and their
+    densities carry +-1 % noise from PCG64(seed) (component-major, x fastest,
+    drawn for the whole lattice) within a cube of half-width 12 cells around
+    the corner; every other cell starts exactly at the background rest
+    state, so the meshed region has a margin of at least 3 resting cells
+    (more than the criterion's shell) and the progressive mesh can reproduce
+    the static one.  The mesh has to grow across the periodic faces."""
+    assert n % 16 == 0 and n >= 48
+    N = n ** 3
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    wrap = lambda v: np.minimum(v, n - v)
+    d = np.sqrt(wrap(x) ** 2 + wrap(y) ** 2 + wrap(z) ** 2).reshape(-1)
+    nb = n // 16
+    edge = lambda v: (v // 16 == 0) | (v // 16 == nb - 1)
+    seeded = (np.maximum(np.maximum(wrap(x), wrap(y)), wrap(z)) <= 12).reshape(-1)
+    bg = np.array([RHO_GAS, 0.1])[:ncomp]
+    rho0 = np.empty((ncomp, N))
+    rho0[0] = RHO_GAS + (RHO_LIQ - RHO_GAS) * 0.5 * (1.0 - np.tanh((d - 8.0) / 2.0))
+    if ncomp == 2:
+        rho0[1] = 0.1
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U = rng.random((ncomp, N))
+    rho0 *= 1.0 + 0.01 * (2.0 * U - 1.0)
+    rho0[:, ~seeded] = bg[:, None]
+    g = ((-1.0, G12), (G12, -1.0)) if ncomp == 2 else ((-1.0, 0.0), (0.0, 0.0))
+    params = dict(FLUID, nx=n, ny=n, nz=n, block=16, ncomp=ncomp, shell_width=2, S=0.0,
+                  bc=(PERIODIC,) * 6, body=((0.0,) * 3,) * 2, g=g,
+                  inlet_rho=(0.0, 0.0), inlet_u=(0.0, 0.0, 0.0), bg_rho=(RHO_GAS, 0.1))
+    b = np.arange(nb)
+    act = (edge(b * 16)[None, None, :] & edge(b * 16)[None, :, None] & edge(b * 16)[:, None, None])
+    return Case(f"seam{n}-c{ncomp}-s{seed}", params, np.zeros(N, np.uint8), rho0, np.zeros((3, N)),
+                act.astype(np.uint8).reshape(-1), steps, dict(seed=seed))
+
+
 def random_spheres(n: int, seed: int, porosity: float = 0.65, rmin: float = 4.0, rmax: float = 12.0,
                    buffer_lo: int = 2, buffer_hi: int = 2, max_attempts: int | None = None,
                    shape: tuple | None = None):
