@@ -38,6 +38,12 @@ K2_BYTES_PER_FLUID_CELL = 2 * 19 * 4 * 2 + 4
 K2_BYTES_PER_FLUID_CELL_F16 = 2 * 19 * 2 * 2 + 16 + 4
 # per solid cell of an active block the kernel reads only the mask word
 K2_BYTES_PER_SOLID_CELL = 4
+# In-place (A-A) pattern, two passes per step.  The collision pass reads and
+# writes the 2 x 19 populations of a fluid cell (304 B), its mask (4 B) and
+# the two pseudo-potentials the first pass stored for it (8 B); the psi pass
+# reads the populations (152 B) and the mask and writes psi (8 B).
+INPLACE_COLLIDE_BYTES_PER_FLUID_CELL = 2 * 19 * 4 * 2 + 4 + 8
+INPLACE_PSI_BYTES_PER_FLUID_CELL = 2 * 19 * 4 + 4 + 8
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_porous192_traffic.json")
@@ -441,6 +447,10 @@ def main():
     ap.add_argument("--channel-tubes", type=int, default=8)
     ap.add_argument("--sample-every", type=int, default=100)
     ap.add_argument("--batch-sims", type=int, default=48)
+    ap.add_argument("--pattern", choices=["ab", "aa"], default="ab",
+                    help="population access pattern: two buffers (ab) or one buffer in place (aa)")
+    ap.add_argument("--inplace-steps", type=int, default=2000,
+                    help="steps of the in-place comparison run (0: skip it)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.last))
@@ -483,9 +493,13 @@ def main():
     K, Wm = args.steps, args.warmup
 
     store = lbm.STORE_F32 if args.store == "f32" else lbm.STORE_F16DEV
+    pattern = lbm.PATTERN_AA if args.pattern == "aa" else lbm.PATTERN_AB
+    if pattern == lbm.PATTERN_AA and store != lbm.STORE_F32:
+        print("bench.py: the in-place pattern stores FP32 populations", file=sys.stderr)
+        sys.exit(2)
 
     def timed_run(progressive: bool):
-        sim = lbm.Simulation(case, progressive=progressive, store=store)
+        sim = lbm.Simulation(case, progressive=progressive, store=store, pattern=pattern)
         sim.step(Wm)
         torch.cuda.synchronize()
         st0 = sim.stats()
@@ -523,13 +537,57 @@ def main():
     times = lbm.lbm_timing_read(sim_s.h)
     lbm.lbm_timing_enable(sim_s.h, False)
     sim_s.close()
-    cnt, tot = times["fused_step"]
+    dominant = "inplace_collide" if pattern == lbm.PATTERN_AA else "fused_step"
+    cnt, tot = times[dominant]
     k2_ms = tot / max(cnt, 1)
     fluid_full = fluid_cells_of_active(case.static_twin(), np.zeros((0, 2), np.int32), 0)
     cells_full = stat["stats"]["n_active"] * 4096
-    per_fluid = K2_BYTES_PER_FLUID_CELL if args.store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
+    if pattern == lbm.PATTERN_AA:
+        per_fluid = INPLACE_COLLIDE_BYTES_PER_FLUID_CELL
+    else:
+        per_fluid = K2_BYTES_PER_FLUID_CELL if args.store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
     k2_bytes = fluid_full * per_fluid + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
+
+    # the in-place pattern on the same full mesh (half the population memory)
+    inplace = None
+    if pattern == lbm.PATTERN_AB and args.store == "f32" and args.inplace_steps > 0:
+        Ki = args.inplace_steps
+        sim_a = lbm.Simulation(case, progressive=False, pattern=lbm.PATTERN_AA)
+        sim_a.step(Wm)
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a0.record()
+        sim_a.step(Ki)
+        a1.record()
+        torch.cuda.synchronize()
+        ms_a = a0.elapsed_time(a1)
+        lbm.lbm_timing_enable(sim_a.h, True)
+        sim_a.step(min(Ki, 200))
+        t_a = lbm.lbm_timing_read(sim_a.h)
+        lbm.lbm_timing_enable(sim_a.h, False)
+        st_a = sim_a.stats()
+        sim_a.close()
+        col_ms = t_a["inplace_collide"][1] / max(t_a["inplace_collide"][0], 1)
+        psi_ms = t_a["inplace_psi"][1] / max(t_a["inplace_psi"][0], 1)
+        col_bytes = (fluid_full * INPLACE_COLLIDE_BYTES_PER_FLUID_CELL
+                     + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
+        psi_bytes = (fluid_full * INPLACE_PSI_BYTES_PER_FLUID_CELL
+                     + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
+        inplace = {
+            "steps": Ki,
+            "ms_per_step": round(ms_a / Ki, 4),
+            "static_active_cell_mlups": round(cells_full * Ki / (ms_a * 1e-3) / 1e6, 2),
+            "over_two_buffer_time": round((ms_a / Ki) / (stat["ms"] / K), 4),
+            "kernel_ms_per_launch": {"inplace_psi": round(psi_ms, 5), "inplace_collide": round(col_ms, 5)},
+            "achieved_gbs": {"inplace_psi": round(psi_bytes / (psi_ms * 1e-3) / 1e9, 1),
+                             "inplace_collide": round(col_bytes / (col_ms * 1e-3) / 1e9, 1)},
+            "bytes_reserved": int(st_a["bytes_reserved"]),
+            "bytes_reserved_two_buffers": int(stat["stats"]["bytes_reserved"]),
+            "leak": int(st_a["leak"]),
+        }
+        print(f"bench: in-place static {Ki} steps {ms_a:.1f} ms, {st_a['bytes_reserved'] / 1e9:.2f} GB "
+              f"vs {stat['stats']['bytes_reserved'] / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
     # achievable HBM rate on this device: a plain 1 GiB device-to-device copy
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -563,9 +621,11 @@ def main():
         "config": {
             "workload": f"porous injection {n}^3, 16^3 blocks, spheres r 4-12, porosity "
                         f"{case.info['porosity']:.3f}, progressive mesh from the inlet blocks, "
-                        + ("FP32" if args.store == "f32" else "FP32 arithmetic, FP16-deviation store"),
+                        + ("FP32" if args.store == "f32" else "FP32 arithmetic, FP16-deviation store")
+                        + (", in-place (A-A) populations" if args.pattern == "aa" else ""),
             "lattice": [n, n, n], "block": 16, "components": 2, "seed": args.seed,
             "store": args.store,
+            "pattern": args.pattern,
             "active_blocks_start": int(prog["active_blocks_per_step"][0]),
             "active_blocks_end": int(prog["active_blocks_per_step"][-1]),
             "fluid_blocks": int(prog["stats"]["n_fluid_blocks"]),
@@ -577,19 +637,21 @@ def main():
         "leak": int(prog["stats"]["leak"]),
         "kernel_ms_per_launch": {k: round(v[1] / max(v[0], 1), 5) for k, v in times.items()},
         "roofline": {
-            "kernel": "fused_step",
+            "kernel": dominant,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic() if (n == 192 and args.store == "f32") else None,
+            "traffic": measured_traffic() if (n == 192 and args.store == "f32" and dominant == "fused_step") else None,
             "bytes_per_launch": int(k2_bytes),
             "launch_ms": round(k2_ms, 5),
             "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
+    if inplace is not None:
+        res["inplace"] = inplace
     if not args.no_cpu:
         import oracle
         threads = min(16, os.cpu_count() or 1)

@@ -51,6 +51,19 @@ extern "C" {
 #define LBM_STORE_F32 0    /* populations stored as FP32 */
 #define LBM_STORE_F16DEV 1 /* populations stored as FP16 deviations from w_i * rho (FP32 math) */
 
+/* ------------------------------------------------------ access patterns */
+/* LBM_PATTERN_AB: two population buffers; each step reads one and writes the
+ *   other (pull streaming, one fused kernel per step).
+ * LBM_PATTERN_AA: one population buffer updated in place (the A-A pattern of
+ *   section 3, which halves the population memory): steps of even index
+ *   read and write each cell's own populations with opposite directions
+ *   swapped, steps of odd index read from and write to the neighbours.  Two
+ *   kernels per step (psi, then collision and streaming).  FP32 store only;
+ *   not with the learned proposal or in batches.  Results are bitwise those
+ *   of LBM_PATTERN_AB. */
+#define LBM_PATTERN_AB 0
+#define LBM_PATTERN_AA 1
+
 /*
  * Run parameters (copied at lbm_create).
  *
@@ -75,7 +88,7 @@ typedef struct lbm_params {
   int32_t store;         /* LBM_STORE_* */
   int32_t progressive;   /* 0: static mesh (every block holding fluid active); 1: progressive */
   int32_t pool_blocks;   /* block slots to reserve; 0 = number of blocks holding fluid */
-  int32_t reserved;      /* must be 0 */
+  int32_t pattern;       /* LBM_PATTERN_* */
   double tau[2];         /* > 0.5 */
   double eos_a, eos_b, eos_R, eos_omega, T_over_Tc;
   double g[2][2];
@@ -195,12 +208,13 @@ int lbm_debug_fields(lbm_t* h, int which, double* out);
 /* Per-kernel GPU timing.  lbm_timing_enable(h, 1) records HIP events around
  * every kernel lbm_step launches (on the handle's stream); lbm_timing_read
  * waits for the stream and returns, per kernel k < n (names from
- * lbm_kernel_name: criterion, activate, init_blocks, fused_step, propose),
- * the launch count and total milliseconds, then resets. */
+ * lbm_kernel_name: criterion, activate, init_blocks, fused_step, propose,
+ * inplace_psi, inplace_collide), the launch count and total milliseconds,
+ * then resets. */
 int lbm_timing_enable(lbm_t* h, int enable);
 int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n);
 const char* lbm_kernel_name(int32_t k);
-#define LBM_NUM_KERNELS 5
+#define LBM_NUM_KERNELS 7
 
 /* Releases every resource of the handle (waits for the stream). */
 int lbm_destroy(lbm_t* h);

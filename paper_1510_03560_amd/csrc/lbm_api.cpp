@@ -23,8 +23,8 @@ using namespace lbm;
 namespace {
 
 constexpr int kTraceCap = 1 << 20;
-const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate", "init_blocks", "fused_step",
-                                                   "propose"};
+const char* const kKernelNames[LBM_NUM_KERNELS] = {"criterion", "activate",    "init_blocks",    "fused_step",
+                                                   "propose",   "inplace_psi", "inplace_collide"};
 
 std::string g_create_error;
 
@@ -179,7 +179,10 @@ int validate(const lbm_params* p) {
     return fail(nullptr, LBM_EINVAL, "store must be LBM_STORE_F32 or LBM_STORE_F16DEV (got %d)", p->store);
   if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
-  if (p->reserved != 0) return fail(nullptr, LBM_EINVAL, "reserved must be 0");
+  if (p->pattern != LBM_PATTERN_AB && p->pattern != LBM_PATTERN_AA)
+    return fail(nullptr, LBM_EINVAL, "pattern must be LBM_PATTERN_AB or LBM_PATTERN_AA");
+  if (p->pattern == LBM_PATTERN_AA && p->store != LBM_STORE_F32)
+    return fail(nullptr, LBM_EINVAL, "pattern LBM_PATTERN_AA needs store LBM_STORE_F32");
   for (int a = 0; a < p->ncomp; ++a) {
     if (!(p->tau[a] > 0.5)) return fail(nullptr, LBM_EINVAL, "tau[%d] must exceed 0.5 (got %g)", a, p->tau[a]);
     if (!(p->bg_rho[a] > 0.0)) return fail(nullptr, LBM_EINVAL, "bg_rho[%d] must be positive", a);
@@ -198,6 +201,21 @@ int check_device_flags(lbm_t* h) {
   if (ctrl[kPoolFull])
     return fail(h, LBM_ENOMEM, "block pool full (%d slots); raise pool_blocks", h->P.capacity);
   return LBM_OK;
+}
+
+bool in_place(const lbm_t* h) { return h->user.pattern == LBM_PATTERN_AA; }
+
+// Where the populations of the current state are read (ReadMode).
+int read_mode(const lbm_t* h) {
+  if (h->step == 0) return kRdOwn;
+  if (!in_place(h)) return kRdPull;
+  return (h->step & 1) ? kRdAAOdd : kRdAAEven;
+}
+
+// How blocks that join before the current step are initialised (InitMode).
+int init_mode(const lbm_t* h) {
+  if (!in_place(h) || h->step == 0) return kInitNatural;
+  return (h->step & 1) ? kInitSwapped : kInitStash;
 }
 
 int sync(lbm_t* h) {
@@ -387,8 +405,10 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   P.plane = (uint32_t)plane;
   const size_t fsz = h->user.store == LBM_STORE_F16DEV ? 2 : 4;
   const bool f16 = h->user.store == LBM_STORE_F16DEV;
+  const bool aa = in_place(h);
   D.f[0] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
-  D.f[1] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
+  D.f[1] = aa ? D.f[0] : dev_alloc(h, fsz * P.ncomp * kQ * plane);
+  D.psi = aa ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
   D.rho[0] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
   D.rho[1] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
   D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * plane);
@@ -404,13 +424,13 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.bfrac = (float*)dev_alloc(h, sizeof(float) * P.nb);
   D.cand = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
   D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
-  if (!D.f[0] || !D.f[1] || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
+  if (!D.f[0] || !D.f[1] || (aa && !D.psi) || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
       !D.slot_block || !D.order || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
       !D.cand || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
-  h->slot_bytes = (int64_t)kCells * ((int64_t)2 * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) + 4 +
-                                     (h->user.progressive ? 12 * P.ncomp : 0));
+  h->slot_bytes = (int64_t)kCells * ((int64_t)(aa ? 1 : 2) * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) +
+                                     (aa ? 4 * P.ncomp : 0) + 4 + (h->user.progressive ? 12 * P.ncomp : 0));
   // initial fields, FP32; NaN marks a component of a cell at the rest state
   if (rho0 || u0) {
     std::vector<float> r((size_t)P.ncomp * N), u(u0 ? (size_t)3 * N : 0);
@@ -448,9 +468,11 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
     HIP_TRY(h, hipEventCreateWithFlags(&h->nact_ev, hipEventDisableTiming));
   }
   HIP_TRY(h, hipMemcpy(D.bfrac, h->bfrac_h.data(), sizeof(float) * P.nb, hipMemcpyHostToDevice));
-  // the rest slot, in both population buffers
-  for (int b = 0; b < 2; ++b) {
-    hipError_t e = launch_init_slots(P, D, b, P.capacity, 1, false, false, h->stream);
+  // the rest slot, in both population buffers (in place: the one buffer,
+  // holding the rest state as post-collision values, opposite pairs swapped)
+  for (int b = 0; b < (aa ? 1 : 2); ++b) {
+    hipError_t e = launch_init_slots(P, D, b, P.capacity, 1, false, false, h->stream,
+                                     aa ? kInitSwapped : kInitNatural, -1);
     if (e != hipSuccess) return fail(h, LBM_EHIP, "init rest slot: %s", hipGetErrorString(e));
   }
   std::vector<int32_t> bslot(P.nb, -1), sblock;
@@ -498,7 +520,8 @@ int lbm_activate(lbm_t* h, const int32_t* ids, int32_t n) {
   const int32_t pending = 1;
   HIP_TRY(h, hipMemcpy(h->D.ctrl + kPending, &pending, sizeof pending, hipMemcpyHostToDevice));
   hipError_t e = launch_activate(h->P, h->D, (int)h->step, h->stream);
-  if (e == hipSuccess) e = launch_init_slots(h->P, h->D, h->rbuf, 0, 0, true, h->step == 0, h->stream);
+  if (e == hipSuccess)
+    e = launch_init_slots(h->P, h->D, h->rbuf, 0, 0, true, h->step == 0, h->stream, init_mode(h), (int)h->step);
   if (e != hipSuccess) return fail(h, LBM_EHIP, "activation: %s", hipGetErrorString(e));
   return sync(h);
 }
@@ -527,8 +550,10 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     const int rc = check_inlet_blocks(h);
     if (rc) return rc;
   }
+  const bool aa = in_place(h);
   for (int32_t k = 0; k < nsteps; ++k) {
     const bool pull = h->step > 0;
+    const int rd = read_mode(h);
     const int rb = h->rbuf;
     int rc;
     if (h->user.progressive && h->nact_pending && hipEventQuery(h->nact_ev) == hipSuccess) {
@@ -540,7 +565,7 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       // join this step
       const int flags = h->step == 0 ? (kCritRecord | kCritExposure)
                                      : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
-      rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, pull, flags, h->stream); });
+      rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, rd, flags, h->stream); });
       if (rc) return rc;
       if (h->prop_enabled) {
         // the learned proposal requests more blocks, ahead of the criterion
@@ -555,18 +580,27 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       }
       rc = timed(h, 1, [&] { return launch_activate(P, h->D, (int)h->step, h->stream); });
       if (rc) return rc;
-      rc = timed(h, 2, [&] { return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream); });
+      rc = timed(h, 2, [&] {
+        return launch_init_slots(P, h->D, rb, 0, 0, true, false, h->stream, init_mode(h), (int)h->step);
+      });
       if (rc) return rc;
     }
-    rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
-    if (rc) return rc;
+    if (aa) {
+      rc = timed(h, 5, [&] { return launch_inplace_psi(P, h->D, rd, h->stream); });
+      if (rc) return rc;
+      rc = timed(h, 6, [&] { return launch_inplace_collide(P, h->D, rd, h->stream); });
+      if (rc) return rc;
+    } else {
+      rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
+      if (rc) return rc;
+    }
     if (h->user.progressive && !h->mesh_complete && !h->nact_pending && h->step % 16 == 0 && h->nact_pinned) {
       HIP_TRY(h, hipMemcpyAsync(h->nact_pinned, h->D.ctrl + kNActive, sizeof(int32_t), hipMemcpyDeviceToHost,
                                 h->stream));
       HIP_TRY(h, hipEventRecord(h->nact_ev, h->stream));
       h->nact_pending = true;
     }
-    h->rbuf ^= 1;
+    if (!aa) h->rbuf ^= 1;
     h->step++;
   }
   return LBM_OK;
@@ -580,7 +614,7 @@ int lbm_sync(lbm_t* h) {
 int lbm_moments_device(lbm_t* h, float* rho, float* u, float* umix) {
   if (!h) return LBM_EINVAL;
   if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_moments before lbm_set_geometry");
-  hipError_t e = launch_export(h->P, h->D, h->rbuf, h->step > 0, rho, u, umix, h->stream);
+  hipError_t e = launch_export(h->P, h->D, h->rbuf, read_mode(h), rho, u, umix, h->stream);
   if (e != hipSuccess) return fail(h, LBM_EHIP, "export: %s", hipGetErrorString(e));
   return LBM_OK;
 }
@@ -657,7 +691,7 @@ int lbm_stats(lbm_t* h, lbm_stats_t* out) {
   if (h->geometry) {
     double m[4] = {0, 0, 0, 0};
     HIP_TRY(h, hipMemsetAsync(h->mass_dev, 0, sizeof m, h->stream));
-    hipError_t e = launch_mass(h->P, h->D, h->rbuf, h->step > 0, h->mass_dev, h->stream);
+    hipError_t e = launch_mass(h->P, h->D, h->rbuf, read_mode(h), h->mass_dev, h->stream);
     if (e != hipSuccess) return fail(h, LBM_EHIP, "mass: %s", hipGetErrorString(e));
     HIP_TRY(h, hipMemcpyAsync(m, h->mass_dev, sizeof m, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -701,7 +735,7 @@ int lbm_debug_fields(lbm_t* h, int which, double* out) {
   }
   hipError_t e = hipMemsetAsync(d_p, 0, sizeof(float) * np, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d_f, 0, sizeof(float) * nf, h->stream);
-  if (e == hipSuccess) e = launch_debug_fields(P, h->D, h->rbuf, h->step > 0, d_s, d_p, d_f, h->stream);
+  if (e == hipSuccess) e = launch_debug_fields(P, h->D, h->rbuf, read_mode(h), d_s, d_p, d_f, h->stream);
   std::vector<float> tmp(which == LBM_DEBUG_PSI ? np : nf);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tmp.data(), which == LBM_DEBUG_PSI ? d_p : d_f, sizeof(float) * tmp.size(),
@@ -740,6 +774,7 @@ int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap) {
   if (!h) return LBM_EINVAL;
   if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_proposal_features before lbm_set_geometry");
   if (cap < 0 || (cap > 0 && (!feat || !block))) return fail(h, LBM_EINVAL, "bad feature buffers");
+  if (in_place(h)) return fail(h, LBM_EINVAL, "the proposal reads two-buffer (LBM_PATTERN_AB) handles only");
   hipError_t e = launch_candidates(h->P, h->D, h->stream);
   if (e == hipSuccess)
     e = launch_propose(h->P, h->D, h->rbuf, h->step > 0, (int)h->step, nullptr, 0.0f, feat, block, cap, h->stream);
@@ -758,6 +793,7 @@ int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t ena
   }
   if (!params) return fail(h, LBM_EINVAL, "proposal parameters missing");
   if (!h->user.progressive) return fail(h, LBM_EINVAL, "the proposal needs a progressive mesh");
+  if (in_place(h)) return fail(h, LBM_EINVAL, "the proposal reads two-buffer (LBM_PATTERN_AB) handles only");
   if (!h->mlp_dev) {
     h->mlp_dev = (float*)dev_alloc(h, sizeof(float) * LBM_MLP_NPARAMS);
     if (!h->mlp_dev) return fail(h, LBM_ENOMEM, "device allocation failed (proposal)");
@@ -796,6 +832,7 @@ int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
     lbm_t* h = hs[i];
     if (!h) return fail(nullptr, LBM_EINVAL, "batch: member %d is NULL", i);
     if (!h->geometry) return fail(nullptr, LBM_ESTATE, "batch: member %d has no geometry", i);
+    if (in_place(h)) return fail(nullptr, LBM_EINVAL, "batch: member %d uses LBM_PATTERN_AA (batches step A-B handles)", i);
     if (h->P.store != h0->P.store || h->P.ncomp != h0->P.ncomp || h->user.progressive != h0->user.progressive)
       return fail(nullptr, LBM_EINVAL, "batch: member %d differs in store, ncomp or mesh mode", i);
     if (h->step != h0->step || h->rbuf != h0->rbuf)

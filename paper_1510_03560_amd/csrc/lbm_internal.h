@@ -16,6 +16,29 @@ constexpr int kMaxComp = 2;
 enum CellKind : uint32_t { kFluid = 0, kSolid = 1, kInlet = 2, kOutlet = 3 };
 constexpr int kKindShift = 24;
 
+// Where a kernel reads the populations f(t) arriving at a cell.
+//  kRdOwn:    at the cell itself, plane i (the initial state, before the first step)
+//  kRdPull:   two buffers: f*_i(x - e_i) at (x - e_i, plane i) of the buffer read
+//  kRdAAEven: one buffer updated in place, after an even number (> 0) of
+//             steps: at (x, plane i), where the last step streamed them
+//  kRdAAOdd:  one buffer, after an odd number of steps: f*_i(x - e_i) at
+//             (x - e_i, plane of the opposite direction), where the last
+//             step left it
+// A bounced link reads the cell's own post-collision value of the opposite
+// direction in every mode.
+enum ReadMode : int { kRdOwn = 0, kRdPull = 1, kRdAAEven = 2, kRdAAOdd = 3 };
+
+// How k_init writes the populations of the slots it initialises.
+//  kInitNatural: f(t) at (x, plane i) (two buffers; in place before the first step)
+//  kInitSwapped: in place, before an odd step: the rest state as post-collision
+//                values, f*_i at (x, opposite plane); also the rest slot
+//  kInitStash:   in place, before an even step (> 0): the rest state at
+//                (x, plane i), except links from a cell of a block that took
+//                part in the last step, which take the value that cell
+//                streamed towards x and kept at its own (x - e_i, opposite
+//                plane); the rest state is left there in its place
+enum InitMode : int { kInitNatural = 0, kInitSwapped = 1, kInitStash = 2 };
+
 // Face kinds (same values as LBM_BC_*).
 enum FaceKind : int { kPeriodic = 0, kWall = 1, kInletFace = 2, kOutletFace = 3 };
 
@@ -64,7 +87,8 @@ struct Params {
 // Device buffers of one handle.
 // A "plane" holds one value per cell of every slot: index slot*4096 + cell.
 struct Buffers {
-  void* f[2];             // populations: [ncomp*19 planes] of float or __half
+  void* f[2];             // populations: [ncomp*19 planes] of float or __half (in place: f[1] == f[0])
+  float* psi;             // in place only: [ncomp planes] pseudo-potential of the step being taken
   float* rho[2];          // FP16 store only: [ncomp planes] reference densities, double-buffered
   uint32_t* mask;         // [1 plane]: bit i = link i bounces; kind in bits 24..25
   float* uprev;           // [ncomp*3 planes] velocity of the previous step (criterion; progressive only)
@@ -102,8 +126,11 @@ struct Batch {
 // [2*19 stored bits][2*19 decoded populations][2 reference densities]
 // [2 densities][2 potentials]; iters = device int.
 hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream);
+// mode: InitMode; born: the step the slots join (blocks activated then are
+// read as rest by kInitStash).
 hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first_slot_host, int count_host,
-                             bool from_device_counts, bool use_initial_fields, hipStream_t stream);
+                             bool from_device_counts, bool use_initial_fields, hipStream_t stream,
+                             int mode = kInitNatural, int born = -1);
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream);
 // Fused step kernel: moments, psi, forces, collision and streaming.
 hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
@@ -114,8 +141,13 @@ enum : int {
   kCritExposure = 4,  // check the psi shown to inactive blocks
   kCritEmission = 8,  // check the populations the last step handed to inactive blocks
 };
-hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, int rd, int flags,
                             hipStream_t stream);
+// In-place step (one population buffer, FP32): psi of every cell of the
+// active blocks into D.psi, then forces, collision and streaming in place.
+// rd: kRdOwn for the first step, then kRdAAOdd / kRdAAEven by step parity.
+hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rd, hipStream_t stream);
+hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rd, hipStream_t stream);
 // Learned activation proposal: list the candidate blocks, then per candidate
 // gather its 12 features; with mlp != nullptr also run the network and request
 // the block when its probability exceeds thr, else write feat[cap][12] and
@@ -130,13 +162,13 @@ hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream);
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
                              hipStream_t stream);
-hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u,
+hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
-hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out2,
+hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, int rd, double* out2,
                        hipStream_t stream);
 // Test dump: psi_slots = device scratch of ncomp planes; psi (ncomp*N) and
 // force (ncomp*3*N) lattice-wide device outputs.
-hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots,
+hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, int rd, float* psi_slots,
                                float* psi, float* force, hipStream_t stream);
 
 }  // namespace lbm

@@ -384,13 +384,14 @@ __host__ __device__ __forceinline__ void pull_axes_z(int z, PullAxes& a) {
   for (int k = 0; k < 3; ++k) a.az[k] = pack_axis(z, k - 1, 9, 2, 13);
 }
 
-template <bool PULL, bool REF>
+template <int RD, bool REF>
 __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t own, uint32_t m, uint32_t plane,
-                                        const int* nslot, Sources<REF>& s) {
+                                        const int* nslot, int rest, Sources<REF>& s) {
+  static_assert(!REF || RD == kRdOwn || RD == kRdPull, "the in-place pattern stores FP32 populations");
   s.fidx[0] = own;
   if constexpr (REF) s.ridx[0] = own;
   const uint32_t own_second = own + plane;
-  if constexpr (!PULL) {
+  if constexpr (RD == kRdOwn) {
     unroll<kQ - 1>([&](auto K) {
       constexpr int i = decltype(K)::value + 1;
       constexpr bool second = !(i & 1);  // plane i is the second of its pair
@@ -414,9 +415,24 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
       constexpr bool second = !(i & 1);  // plane i is the second of its pair
       const uint32_t src_cell = ((uint32_t)slot[i] << 12) | (w[i] & 0xFFFFu);
       const bool bounce = (m >> i) & 1u;
-      // bounced: the cell's own population of the opposite direction, which
-      // is the other plane of the pair
-      s.fidx[i] = bounce ? (second ? own : own_second) : (second ? src_cell + plane : src_cell);
+      const uint32_t own_i = second ? own_second : own;   // (x, plane i)
+      const uint32_t own_o = second ? own : own_second;   // (x, plane of the opposite direction)
+      const uint32_t src_i = second ? src_cell + plane : src_cell;
+      const uint32_t src_o = second ? src_cell : src_cell + plane;
+      if constexpr (RD == kRdPull) {
+        // bounced: the cell's own population of the opposite direction, which
+        // is the other plane of the pair
+        s.fidx[i] = bounce ? own_o : src_i;
+      } else if constexpr (RD == kRdAAOdd) {
+        // f*_i(x - e_i) sits at (x - e_i, opposite plane); a bounced link's
+        // value at (x, plane i)
+        s.fidx[i] = bounce ? own_i : src_o;
+      } else {
+        // streamed in place to (x, plane i); a link from a block that did
+        // not take part in the last step carries the rest state, read from
+        // the rest slot (which stores it swapped, like a post-collision cell)
+        s.fidx[i] = (bounce || slot[i] != rest) ? own_i : src_o;
+      }
       if constexpr (REF) s.ridx[i] = bounce ? own : src_cell;
     });
   }
@@ -618,12 +634,13 @@ __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) 
 
 // ----------------------------------------------------------- slot init
 // Initialises slots [first, first+count): per-cell mask (links that bounce,
-// cell kind), populations of buffer `buf`, psi, reference densities and the
-// criterion history.  Slot `capacity` (the rest slot) is initialised the same
-// way with the rest state everywhere and an all-fluid mask.
+// cell kind), populations of buffer `buf` (placed as `mode` says), psi,
+// reference densities and the criterion history.  Slot `capacity` (the rest
+// slot) is initialised the same way with the rest state everywhere and an
+// all-fluid mask.
 template <typename S>
 __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, int first_h, int count_h, int from_dev,
-                                              int use_init, Batch Bt) {
+                                              int use_init, Batch Bt, int mode, int born) {
   // batched: blockIdx.y selects the simulation
   const bool batched = Bt.nsims > 0;
   const Params& P = batched ? Bt.P[blockIdx.y] : Pv;
@@ -675,6 +692,25 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
         });
       }
       D.mask[cid] = m;
+      // in place, before an even step: the links whose source cell lies in a
+      // block that took part in the last step (active, not joining now)
+      // take what that cell streamed towards this one (each such value has
+      // one receiving link, so one thread moves it)
+      uint32_t stash[kQ];
+      for (int i = 0; i < kQ; ++i) stash[i] = ~0u;
+      if (mode == kInitStash && !rest_slot && ((m >> kKindShift) & 3u) != kSolid) {
+        const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
+        for (int i = 1; i < kQ; ++i) {
+          if ((m >> i) & 1u) continue;  // bounced: rest, like every link from a solid cell
+          const int sx = (X - dir_ex(i) + P.nx) % P.nx, sy = (Y - dir_ey(i) + P.ny) % P.ny,
+                    sz = (Z - dir_ez(i) + P.nz) % P.nz;
+          const int nbk = sx / kB + P.nbx * (sy / kB + P.nby * (sz / kB));
+          const int sl = D.block_slot[nbk];
+          if (sl >= 0 && D.act_step[nbk] != born) stash[i] = (uint32_t)sl * kCells + cell_of(sx & 15, sy & 15, sz & 15);
+        }
+      }
+      if (D.psi)
+        for (int a = 0; a < P.ncomp; ++a) D.psi[(size_t)a * plane + cid] = P.psi_rest[a];
       for (int a = 0; a < P.ncomp; ++a) {
         float r0 = __int_as_float(0x7fc00000);  // NaN: rest state
         float ux = 0.0f, uy = 0.0f, uz = 0.0f;
@@ -691,8 +727,17 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
         for (int i = 0; i < kQ; ++i) fe[i] = at_rest ? 0.0f : feq_dir(i, r0, ux, uy, uz);
         // reference density of the FP16 store: the cell's own density
         const float rref = at_rest ? P.rho_ref_rest[a] : moments(fe).rho;
-        for (int i = 0; i < kQ; ++i)
-          fb[(size_t)(a * kQ + i) * plane + cid] = at_rest ? rest_stored<S>(P, a, i) : S::encode(fe[i], dir_w(i) * rref);
+        for (int i = 0; i < kQ; ++i) {
+          typename S::T v = at_rest ? rest_stored<S>(P, a, mode == kInitSwapped ? dir_opp(i) : i)
+                                    : S::encode(fe[i], dir_w(i) * rref);
+          if (stash[i] != ~0u) {
+            // moved here; the sender's address reads as the rest state again
+            typename S::T* sp = fb + (size_t)(a * kQ + dir_opp(i)) * plane + stash[i];
+            v = *sp;
+            *sp = rest_stored<S>(P, a, dir_opp(i));
+          }
+          fb[(size_t)(a * kQ + i) * plane + cid] = v;
+        }
         if constexpr (S::kRef) {
           D.rho[0][(size_t)a * plane + cid] = rref;
           D.rho[1][(size_t)a * plane + cid] = rref;
@@ -708,7 +753,7 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
 // Test dump, first pass: psi (Eq 6-7) of every non-solid cell of the active
 // blocks into a slot-indexed buffer, exactly as the step computes it (pulled
 // densities; inlet nodes psi(inlet density), outlet nodes the rest value).
-template <typename S, int NC, bool PULL>
+template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int rbuf, float* psi_out) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
@@ -732,7 +777,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
     if (kind == kSolid) continue;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
@@ -868,7 +913,7 @@ constexpr int kHalo = kH * kH * kH;   // 5832 cells
 
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (x + 1) + kH * ((y + 1) + kH * (z + 1)); }
 
-template <typename S, int NC, bool PULL>
+template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, int rbuf, const float* psi_slots,
                                                           float* dbg_psi, float* dbg_force) {
   const int n_active = D.ctrl[kNActive];
@@ -922,7 +967,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
                              F);
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
     const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
@@ -1104,7 +1149,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
         if (pull) {
           Sources<S::kRef> src;
           pull_axes_z(z, pa);
-          sources<PULL, S::kRef>(pa, cell, m, plane, ctx.nslot, src);
+          sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cell, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
           for (int a = 0; a < NC; ++a) {
             if constexpr (S::kRef) {
@@ -1217,6 +1262,196 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
 }
 
+// ------------------------------------------------------- in-place step
+// The A-A access pattern (section 3): one population buffer, updated in
+// place.  A step of even index reads f(t) at each cell's own address and
+// writes f* back to the same cell with each opposite pair swapped; a step of
+// odd index reads f*_i(x - e_i) at the neighbour's swapped address and writes
+// f*_i(x) into the neighbour x + e_i at its natural address, so that after
+// every second step the populations are in natural order again.  Each
+// address a step reads is written by the thread that read it, after the
+// read, so no second buffer is needed; the pseudo-potential of the
+// neighbours (Eq 8-9), however, has to be taken before any of them is
+// overwritten, so the step runs as two passes: k_inplace_psi stores psi of
+// every cell of the active blocks, k_inplace_collide takes the forces from
+// it, collides and streams.  The arithmetic of each cell is that of k_fused,
+// in the same order, so both patterns give the same bits.
+//
+// Progressive mesh: a link from a cell of an inactive block carries the rest
+// state.  At a step of odd index a population streamed towards a block that
+// is inactive stays at the sender's own swapped address (nothing else writes
+// there), which the next step reads as the rest state (kRdAAEven: the link's
+// source is inactive).  If that block joins the next step, its
+// initialisation moves the value to the receiving cell and leaves the rest
+// state in its place (kInitStash).
+
+constexpr int kInplaceThreads = 256;
+
+// Pass 1: psi (Eq 6-7) of every cell of the active blocks (fluid cells from
+// their densities, inlet nodes psi(inlet density), outlet and solid cells the
+// rest value) into D.psi.
+template <int NC, int RD>
+__global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D) {
+  const int n_active = D.ctrl[kNActive];
+  const int g = slot_of_workgroup(blockIdx.x, n_active);
+  if (g >= n_active) return;
+  const int s = D.order[g];
+  __shared__ BlockCtx ctx;
+  setup_block(P, D, D.slot_block[s], ctx);
+  __syncthreads();
+  int x, y, z0;
+  cell_xyz((int)threadIdx.x, x, y, z0);
+  PullAxes pa;
+  pull_axes_xy(x, y, pa);
+  const uint32_t plane = P.plane;
+  const float* __restrict__ fb = static_cast<const float*>(D.f[0]);
+  const uint32_t own_base = (uint32_t)s * kCells;
+  unsigned numeric = 0u, clamps = 0u;
+#pragma unroll 1
+  for (int z = z0; z < kB; z += kZStep) {
+    const uint32_t cid = own_base + cell_of(x, y, z);
+    const uint32_t m = ld(D.mask, cid * 4u);
+    const uint32_t kind = (m >> kKindShift) & 3u;
+    float psi[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) psi[a] = kind == kInlet ? P.psi_in[a] : P.psi_rest[a];
+    if (kind == kFluid) {
+      Sources<false> src;
+      pull_axes_z(z, pa);
+      sources<RD, false>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        float f[kQ];
+        gather<StoreF32>(fb, plane, a, src, nullptr, f);
+        const float rho = moments(f).rho;
+        bool cl;
+        psi[a] = pseudo_potential(P, a, rho, cl);
+        clamps += cl ? 1u : 0u;
+        if (!(rho > 0.0f && rho < 3.0e38f)) numeric = 1u;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NC; ++a) st(D.psi + (size_t)a * plane, cid * 4u, psi[a]);
+  }
+  if (numeric) atomicOr(&D.ctrl[kNumeric], 1);
+  if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
+}
+
+// Pass 2: forces (Eq 8-9, psi of an 18 x 18 footprint in an LDS ring of four
+// planes), collision (Eq 10-12) and in-place streaming.  One workgroup per
+// active block; thread t owns column t of the block and sweeps z = 0 .. 15.
+// Inlet and outlet nodes stream their imposed state and solid cells write the
+// rest state to their own address, which nothing reads.
+template <int NC, int RD>
+__global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, Buffers D) {
+  static_assert(RD != kRdPull, "the in-place step reads in place");
+  constexpr bool kOdd = RD == kRdAAOdd;
+  const int n_active = D.ctrl[kNActive];
+  const int g = slot_of_workgroup(blockIdx.x, n_active);
+  if (g >= n_active) return;
+  const int s = D.order[g];
+  __shared__ BlockCtx ctx;
+  __shared__ float psi_s[kPsiRing][NC][kFoot];
+  __shared__ float f_in_s[NC][kQ], f_rest_s[NC][kQ];
+  setup_block(P, D, D.slot_block[s], ctx);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + NC * kQ) {
+    const int k = threadIdx.x - 64, a = k / kQ, i = k % kQ;
+    f_in_s[a][i] = P.f_in[a][i];
+    f_rest_s[a][i] = P.f_rest[a][i];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  int cx, cy, cz0;
+  cell_xyz(t, cx, cy, cz0);
+  const int hp = (cy + 1) * kH + (cx + 1);
+  const uint32_t plane = P.plane;
+  float* __restrict__ fb = static_cast<float*>(D.f[0]);
+  const float* __restrict__ psi_g = D.psi;
+  const uint32_t own_base = (uint32_t)s * kCells;
+  // psi of footprint plane zp (x, y in [-1, 16]) into ring slot zp & 3;
+  // inactive neighbours read the rest slot, which holds psi_rest
+  auto psi_load = [&](int zp) {
+    for (int e = t; e < NC * kFoot; e += kInplaceThreads) {
+      const int a = e / kFoot, col = e % kFoot;
+      const int hx = col % kH - 1, hy = col / kH - 1;
+      const int slot = ctx.nslot[13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(zp)];
+      psi_s[zp & 3][a][col] =
+          ld(psi_g + (size_t)a * plane, ((uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u);
+    }
+  };
+  psi_load(-1);
+  psi_load(0);
+  PullAxes pa;
+  pull_axes_xy(cx, cy, pa);
+#pragma unroll 1
+  for (int z = 0; z < kB; ++z) {
+    // (ring slot (z + 1) & 3 was last read two planes ago, before the
+    // previous barrier)
+    psi_load(z + 1);
+    __syncthreads();
+    const uint32_t cid = own_base + cell_of(cx, cy, z);
+    const uint32_t m = ld(D.mask, cid * 4u);
+    const uint32_t kind = (m >> kKindShift) & 3u;
+    pull_axes_z(z, pa);
+    float fp[NC][kQ];
+    if (kind == kFluid) {
+      Sources<false> src;
+      sources<RD, false>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) gather<StoreF32>(fb, plane, a, src, nullptr, fp[a]);
+      float psi_c[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[z & 3][a][hp];
+      Vec3 F[NC];
+      interaction_forces<NC>(P, psi_c,
+                             [&](int a, int i) {
+                               const int hn = hp + dir_ex(i) + kH * dir_ey(i);
+                               const bool solid_nb = (m >> dir_opp(i)) & 1u;  // x + e_i solid or outside
+                               return solid_nb ? psi_c[a] : psi_s[(z + dir_ez(i)) & 3][a][hn];
+                             },
+                             F);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        const Mom mo = moments(fp[a]);
+        collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho),
+                     [&](auto I, float v) { fp[a][decltype(I)::value] = v; });
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) fp[a][i] = kind == kInlet ? f_in_s[a][i] : f_rest_s[a][i];
+    }
+    // destination of f*_i: even index, the cell's own swapped address; odd
+    // index, x + e_i at its natural address, or the own swapped address when
+    // x + e_i is solid, outside or in an inactive block, or x is solid
+    uint32_t dst[kQ];
+    dst[0] = cid;
+    unroll<kQ - 1>([&](auto K) {
+      constexpr int i = decltype(K)::value + 1;
+      constexpr bool second = !(i & 1);
+      const uint32_t own_o = second ? cid : cid + plane;
+      if constexpr (!kOdd) {
+        dst[i] = own_o;
+      } else {
+        const uint32_t w = pa.ax[1 + dir_ex(i)] + pa.ay[1 + dir_ey(i)] + pa.az[1 + dir_ez(i)];  // x + e_i
+        const int tslot = ctx.nslot[w >> 16];
+        const bool keep = kind == kSolid || ((m >> dir_opp(i)) & 1u) || tslot == P.capacity;
+        const uint32_t tcell = ((uint32_t)tslot << 12) | (w & 0xFFFFu);
+        dst[i] = keep ? own_o : (second ? tcell + plane : tcell);
+      }
+    });
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      unroll<kQ>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
+      });
+    }
+  }
+}
+
 // ------------------------------------------------------------- criterion
 // Eq 13 on frontier blocks only (section 4.2): a fluid cell within `shell`
 // cells of an inactive neighbour block that holds fluid, whose velocity
@@ -1238,7 +1473,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
 // The shell cells of a block are first compacted into an LDS list (in any
 // order: every result is a per-cell store, an integer atomic or a bit OR), so
 // that all threads work on them together.
-template <typename S, int NC, bool PULL, bool BATCH>
+template <typename S, int NC, int RD, bool BATCH>
 __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, int rbuf, int flags, Batch Bt) {
   int sim = 0, s;
   if constexpr (BATCH) {
@@ -1309,10 +1544,12 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
         unroll<kQ - 1>([&](auto I) {
           constexpr int i = decltype(I)::value + 1;
           constexpr int first = (i & 1) ? i : i - 1;
-          constexpr bool second = !(i & 1);
+          // f*_i(x) is stored at (x, plane i), or with the in-place pattern
+          // at (x, opposite plane) after either parity of step
+          constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
           if ((out_links >> i) & 1u) {
             const typename S::T v = ld(fb + (size_t)(a * kQ + first) * plane,
-                                       (cid + (second ? plane : 0u)) * (uint32_t)sizeof(typename S::T));
+                                       (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(typename S::T));
             if (S::bits(v) != P.f_rest_bits[a][i]) bad |= 1u << i;
           }
         });
@@ -1327,7 +1564,7 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
       pull_axes_xy(x, y, pa);
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
-      sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
       bool changed = false, psi_differs = false;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
@@ -1505,7 +1742,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
       pull_axes_xy(x, y, pa);
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
-      sources<PULL, S::kRef>(pa, cid, m, plane, nslotB, src);
+      sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cid, m, plane, nslotB, P.capacity, src);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         float f[kQ];
@@ -1604,7 +1841,7 @@ __global__ void k_fill_default(Params P, Buffers D, float* rho, float* u, float*
 }
 
 // Moments (Eq 4-5) of the active blocks into lattice-wide arrays.
-template <typename S, int NC, bool PULL>
+template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rbuf, float* rho, float* u,
                                                       float* umix) {
   const int n_active = D.ctrl[kNActive];
@@ -1633,7 +1870,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
     float mr = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       Mom mo = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1667,7 +1904,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
 
 // Sum of rho_a over the fluid cells of the active blocks, FP64; out[2]
 // counts those cells.
-template <typename S, int NC, bool PULL>
+template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf, double* out) {
   const int n_active = D.ctrl[kNActive];
   const int s = slot_of_workgroup(blockIdx.x, n_active);
@@ -1695,7 +1932,7 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
     ++nf;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<PULL, S::kRef>(pa, cid, m, plane, ctx.nslot, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
@@ -1719,6 +1956,19 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
   }
 }
 
+// Calls fn with the read mode rd as a compile-time constant (the in-place
+// modes exist for the FP32 store only).
+template <typename S, typename Fn>
+hipError_t with_rd(int rd, Fn&& fn) {
+  if (rd == kRdOwn) return fn(std::integral_constant<int, kRdOwn>{});
+  if (rd == kRdPull) return fn(std::integral_constant<int, kRdPull>{});
+  if constexpr (!S::kRef) {
+    if (rd == kRdAAEven) return fn(std::integral_constant<int, kRdAAEven>{});
+    if (rd == kRdAAOdd) return fn(std::integral_constant<int, kRdAAOdd>{});
+  }
+  return hipErrorInvalidValue;
+}
+
 // Dispatch on storage format and component count.
 template <template <typename, int> class K, typename... A>
 hipError_t dispatch(const Params& P, A&&... args) {
@@ -1740,26 +1990,24 @@ struct RestL {
 template <typename S, int NC>
 struct InitL {
   static hipError_t launch(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
-                           bool use_init, hipStream_t st) {
+                           bool use_init, int mode, int born, hipStream_t st) {
     const int grid = from_dev ? 512 : (count > 0 ? (count < 4096 ? count : 4096) : 1);
     hipLaunchKernelGGL((k_init<S>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
-                       use_init ? 1 : 0, Batch{});
+                       use_init ? 1 : 0, Batch{}, mode, born);
     return hipGetLastError();
   }
 };
 template <typename S, int NC>
 struct DebugL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots, float* dp,
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, float* psi_slots, float* dp,
                            float* df, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kThreads);
-    if (pull) {
-      hipLaunchKernelGGL((k_debug_psi<S, NC, true>), g, b, 0, st, P, D, rbuf, psi_slots);
-      hipLaunchKernelGGL((k_debug_force<S, NC, true>), g, b, 0, st, P, D, rbuf, psi_slots, dp, df);
-    } else {
-      hipLaunchKernelGGL((k_debug_psi<S, NC, false>), g, b, 0, st, P, D, rbuf, psi_slots);
-      hipLaunchKernelGGL((k_debug_force<S, NC, false>), g, b, 0, st, P, D, rbuf, psi_slots, dp, df);
-    }
-    return hipGetLastError();
+    return with_rd<S>(rd, [&](auto R) {
+      constexpr int M = decltype(R)::value;
+      hipLaunchKernelGGL((k_debug_psi<S, NC, M>), g, b, 0, st, P, D, rbuf, psi_slots);
+      hipLaunchKernelGGL((k_debug_force<S, NC, M>), g, b, 0, st, P, D, rbuf, psi_slots, dp, df);
+      return hipGetLastError();
+    });
   }
 };
 template <typename S, int NC>
@@ -1775,13 +2023,34 @@ struct FusedL {
 };
 template <typename S, int NC>
 struct CriterionL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int flags, hipStream_t st) {
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, int flags, hipStream_t st) {
     const dim3 g(grid_for(P.capacity)), b(kThreads);
-    if (pull)
-      hipLaunchKernelGGL((k_criterion<S, NC, true, false>), g, b, 0, st, P, D, rbuf, flags, Batch{});
-    else
-      hipLaunchKernelGGL((k_criterion<S, NC, false, false>), g, b, 0, st, P, D, rbuf, flags, Batch{});
-    return hipGetLastError();
+    return with_rd<S>(rd, [&](auto R) {
+      hipLaunchKernelGGL((k_criterion<S, NC, decltype(R)::value, false>), g, b, 0, st, P, D, rbuf, flags, Batch{});
+      return hipGetLastError();
+    });
+  }
+};
+template <typename S, int NC>
+struct InplaceL {
+  static hipError_t launch(const Params& P, const Buffers& D, int rd, bool collide_pass, hipStream_t st) {
+    if constexpr (S::kRef) {
+      return hipErrorInvalidValue;  // the in-place pattern stores FP32 populations
+    } else {
+      const dim3 g(grid_for(P.capacity));
+      return with_rd<S>(rd, [&](auto R) {
+        constexpr int M = decltype(R)::value;
+        if constexpr (M == kRdPull) {
+          return hipErrorInvalidValue;
+        } else {
+          if (collide_pass)
+            hipLaunchKernelGGL((k_inplace_collide<NC, M>), g, dim3(kInplaceThreads), 0, st, P, D);
+          else
+            hipLaunchKernelGGL((k_inplace_psi<NC, M>), g, dim3(kThreads), 0, st, P, D);
+          return hipGetLastError();
+        }
+      });
+    }
   }
 };
 template <typename S, int NC>
@@ -1820,11 +2089,12 @@ struct BatchL {
       const int flags = first ? (kCritRecord | kCritExposure)
                               : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
       if (first)
-        hipLaunchKernelGGL((k_criterion<S, NC, false, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
+        hipLaunchKernelGGL((k_criterion<S, NC, kRdOwn, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
       else
-        hipLaunchKernelGGL((k_criterion<S, NC, true, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
+        hipLaunchKernelGGL((k_criterion<S, NC, kRdPull, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
       hipLaunchKernelGGL((k_activate<true>), dim3(B.nsims), dim3(1024), 0, st, P0, Buffers{}, 0, B);
-      hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B);
+      hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
+                         (int)kInitNatural, -1);
       hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
     }
     if (first)
@@ -1837,24 +2107,24 @@ struct BatchL {
 };
 template <typename S, int NC>
 struct ExportL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, float* r, float* u, float* m,
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, float* r, float* u, float* m,
                            hipStream_t st) {
     hipLaunchKernelGGL(k_fill_default, dim3(2048), dim3(256), 0, st, P, D, r, u, m);
-    if (pull)
-      hipLaunchKernelGGL((k_export<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, r, u, m);
-    else
-      hipLaunchKernelGGL((k_export<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, r, u, m);
-    return hipGetLastError();
+    return with_rd<S>(rd, [&](auto R) {
+      hipLaunchKernelGGL((k_export<S, NC, decltype(R)::value>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P,
+                         D, rbuf, r, u, m);
+      return hipGetLastError();
+    });
   }
 };
 template <typename S, int NC>
 struct MassL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, double* out, hipStream_t st) {
-    if (pull)
-      hipLaunchKernelGGL((k_mass<S, NC, true>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, out);
-    else
-      hipLaunchKernelGGL((k_mass<S, NC, false>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D, rbuf, out);
-    return hipGetLastError();
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, double* out, hipStream_t st) {
+    return with_rd<S>(rd, [&](auto R) {
+      hipLaunchKernelGGL((k_mass<S, NC, decltype(R)::value>), dim3(grid_for(P.capacity)), dim3(kThreads), 0, st, P, D,
+                         rbuf, out);
+      return hipGetLastError();
+    });
   }
 };
 
@@ -1866,8 +2136,8 @@ hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* 
 }
 
 hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
-                             bool use_init, hipStream_t stream) {
-  return dispatch<InitL>(P, D, buf, first, count, from_dev, use_init, stream);
+                             bool use_init, hipStream_t stream, int mode, int born) {
+  return dispatch<InitL>(P, D, buf, first, count, from_dev, use_init, mode, born, stream);
 }
 
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream) {
@@ -1879,9 +2149,17 @@ hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, 
   return dispatch<FusedL>(P, D, rbuf, pull, stream);
 }
 
-hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, bool pull, int flags,
+hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, int rd, int flags,
                             hipStream_t stream) {
-  return dispatch<CriterionL>(P, D, rbuf, pull, flags, stream);
+  return dispatch<CriterionL>(P, D, rbuf, rd, flags, stream);
+}
+
+hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rd, hipStream_t stream) {
+  return dispatch<InplaceL>(P, D, rd, false, stream);
+}
+
+hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rd, hipStream_t stream) {
+  return dispatch<InplaceL>(P, D, rd, true, stream);
 }
 
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream) {
@@ -1905,18 +2183,18 @@ hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull
   return dispatch<ProposeL>(P, D, rbuf, pull, step, mlp, thr, feat, block, cap, stream);
 }
 
-hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, bool pull, float* rho, float* u, float* umix,
+hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u, float* umix,
                          hipStream_t stream) {
-  return dispatch<ExportL>(P, D, rbuf, pull, rho, u, umix, stream);
+  return dispatch<ExportL>(P, D, rbuf, rd, rho, u, umix, stream);
 }
 
-hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, bool pull, double* out, hipStream_t stream) {
-  return dispatch<MassL>(P, D, rbuf, pull, out, stream);
+hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, int rd, double* out, hipStream_t stream) {
+  return dispatch<MassL>(P, D, rbuf, rd, out, stream);
 }
 
-hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, bool pull, float* psi_slots, float* psi,
+hipError_t launch_debug_fields(const Params& P, const Buffers& D, int rbuf, int rd, float* psi_slots, float* psi,
                                float* force, hipStream_t stream) {
-  return dispatch<DebugL>(P, D, rbuf, pull, psi_slots, psi, force, stream);
+  return dispatch<DebugL>(P, D, rbuf, rd, psi_slots, psi, force, stream);
 }
 
 }  // namespace lbm

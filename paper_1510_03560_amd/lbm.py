@@ -18,6 +18,8 @@ from . import _build
 
 PERIODIC, WALL, INLET, OUTLET = 0, 1, 2, 3
 STORE_F32, STORE_F16DEV = 0, 1
+PATTERN_AB, PATTERN_AA = 0, 1
+NUM_KERNELS = 7
 DEBUG_PSI, DEBUG_FORCE = 0, 1
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EHIP", -5: "ENUMERIC"}
 
@@ -32,7 +34,7 @@ class lbm_params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("block", C.c_int32),
         ("ncomp", C.c_int32), ("shell_width", C.c_int32), ("bc", C.c_int32 * 6),
-        ("store", C.c_int32), ("progressive", C.c_int32), ("pool_blocks", C.c_int32), ("reserved", C.c_int32),
+        ("store", C.c_int32), ("progressive", C.c_int32), ("pool_blocks", C.c_int32), ("pattern", C.c_int32),
         ("tau", C.c_double * 2),
         ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_omega", C.c_double),
         ("T_over_Tc", C.c_double), ("g", (C.c_double * 2) * 2), ("beta", C.c_double), ("S", C.c_double),
@@ -108,7 +110,8 @@ def _ptr(a, ct):
     return None if a is None else a.ctypes.data_as(C.POINTER(ct))
 
 
-def make_params(p: dict, store: int = STORE_F32, progressive: bool | None = None, pool_blocks: int = 0) -> lbm_params:
+def make_params(p: dict, store: int = STORE_F32, progressive: bool | None = None, pool_blocks: int = 0,
+                pattern: int = PATTERN_AB) -> lbm_params:
     """lbm_params from the plain parameter dict of the workload generators."""
     s = lbm_params()
     s.nx, s.ny, s.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
@@ -120,7 +123,7 @@ def make_params(p: dict, store: int = STORE_F32, progressive: bool | None = None
     s.store = int(store)
     s.progressive = int(bool(progressive)) if progressive is not None else 0
     s.pool_blocks = int(pool_blocks)
-    s.reserved = 0
+    s.pattern = int(pattern)
     for a in range(2):
         s.tau[a] = float(p["tau"][a])
         s.inlet_rho[a] = float(p["inlet_rho"][a])
@@ -202,7 +205,7 @@ def lbm_timing_enable(h, enable: bool):
     _check(load().lbm_timing_enable(h, int(bool(enable))), h)
 
 
-def lbm_timing_read(h, n: int = 5):
+def lbm_timing_read(h, n: int = NUM_KERNELS):
     counts = np.zeros(n, dtype=np.int64)
     ms = np.zeros(n)
     _check(load().lbm_timing_read(h, _ptr(counts, C.c_int64), _ptr(ms, C.c_double), n), h)
@@ -234,15 +237,17 @@ class Simulation:
 
     case: a workloads.Case (params dict, solid, rho0, u0, active_blocks).
     store: STORE_F32 or STORE_F16DEV.  progressive: defaults to
-    case.active_blocks is not None.
+    case.active_blocks is not None.  pattern: PATTERN_AB (two population
+    buffers) or PATTERN_AA (one buffer updated in place).
     """
 
     def __init__(self, case, store: int = STORE_F32, progressive: bool | None = None, pool_blocks: int = 0,
-                 stream=None):
+                 stream=None, pattern: int = PATTERN_AB):
         if progressive is None:
             progressive = case.active_blocks is not None
         self.case = case
-        self.params = make_params(case.params, store=store, progressive=progressive, pool_blocks=pool_blocks)
+        self.params = make_params(case.params, store=store, progressive=progressive, pool_blocks=pool_blocks,
+                                  pattern=pattern)
         self.ncomp = self.params.ncomp
         self.N = self.params.nx * self.params.ny * self.params.nz
         self.h = lbm_create(self.params, stream=stream if stream is not None else torch_stream())

@@ -91,7 +91,7 @@ def test_struct_layout_matches_header(L, tmp_path):
     ("ncomp", 3, "ncomp"),
     ("shell_width", 0, "shell_width"),
     ("store", 7, "store"),
-    ("reserved", 1, "reserved"),
+    ("pattern", 2, "pattern"),
 ])
 def test_invalid_params_rejected_without_gpu(L, field, value, needle):
     p = L.make_params(W.droplet_periodic(32, 0).params)
@@ -100,6 +100,23 @@ def test_invalid_params_rejected_without_gpu(L, field, value, needle):
         L.lbm_create(p, stream=0)
     assert ei.value.code == -1
     assert needle in str(ei.value)
+
+
+def test_in_place_pattern_needs_fp32_store(L):
+    """The in-place pattern stores FP32 populations only; the check comes
+    before any device work."""
+    p = L.make_params(W.droplet_periodic(32, 0).params, store=L.STORE_F16DEV, pattern=L.PATTERN_AA)
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_create(p, stream=0)
+    assert ei.value.code == -1 and "LBM_STORE_F32" in str(ei.value)
+
+
+def test_kernel_names_cover_both_patterns(L):
+    lib = L.load()
+    names = [lib.lbm_kernel_name(k).decode() for k in range(L.NUM_KERNELS)]
+    assert names == ["criterion", "activate", "init_blocks", "fused_step", "propose", "inplace_psi",
+                     "inplace_collide"]
+    assert lib.lbm_kernel_name(L.NUM_KERNELS).decode() == ""
 
 
 def test_tau_and_periodic_pairs_rejected(L):

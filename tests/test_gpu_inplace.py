@@ -1,0 +1,182 @@
+"""The in-place (A-A) access pattern through the C ABI: one population buffer
+updated in place (section 3).  Its kernels carry out the arithmetic of the
+two-buffer step in the same order, so every field must equal the two-buffer
+run to the bit, after odd and even step counts, on static and progressive
+meshes (blocks joining at both step parities, by the criterion and by the
+caller), with walls, inlet and outlet, one or two components; and the FP64
+oracle bounds both."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1510_03560_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_03560_amd import lbm as L
+    L.load()
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    return L
+
+
+def rel_linf(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def run(lbm, case, plan, pattern, progressive=None):
+    """plan: list of ("step", n) / ("activate", block ids) / ("check",);
+    returns the fields, psi/force dumps and stats at every check."""
+    sim = lbm.Simulation(case, progressive=progressive, pattern=pattern)
+    out = []
+    try:
+        for item in plan:
+            if item[0] == "step":
+                sim.step(item[1])
+            elif item[0] == "activate":
+                sim.activate(item[1])
+            else:
+                out.append((sim.moments(), sim.debug_fields(), sim.stats(), sim.trace()))
+    finally:
+        sim.close()
+    return out
+
+
+def assert_same(ab, aa):
+    for (m1, d1, s1, t1), (m2, d2, s2, t2) in zip(ab, aa):
+        for x, y in zip(m1, m2):
+            assert np.array_equal(x, y)
+        for x, y in zip(d1, d2):
+            assert np.array_equal(x, y)
+        assert np.array_equal(t1, t2)
+        for k in ("steps", "n_active", "leak", "clamps", "activations", "numeric_error"):
+            assert s1[k] == s2[k], k
+        assert s1["mass"] == s2["mass"]
+
+
+def test_static_droplet_equals_two_buffers_bitwise(lbm):
+    c = W.droplet_periodic(32, 1)
+    plan = [("check",), ("step", 1), ("check",), ("step", 1), ("check",), ("step", 5), ("check",),
+            ("step", 13), ("check",)]
+    ab = run(lbm, c, plan, lbm.PATTERN_AB)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    assert_same(ab, aa)
+    # and the oracle, after the 20 steps
+    ref = oracle.Sim(c.params, c.solid, c.rho0, c.u0, None)
+    ref.step(20)
+    rr, ur, _, _ = ref.moments()
+    rho, u = aa[-1][0][0], aa[-1][0][1]
+    for a in range(2):
+        assert rel_linf(rho[a], rr[a]) <= 1e-5
+    assert rel_linf(u, ur) <= 1e-5
+
+
+@pytest.mark.parametrize("steps", [61, 80])
+def test_progressive_porous_equals_two_buffers_bitwise(lbm, steps):
+    """Porous injection at 64^3 (inlet, outlet, walls): the mesh grows from
+    the inlet blocks, blocks join after steps of both parities."""
+    c = W.porous_injection(64, seed=2)
+    plan = [("step", 17), ("check",), ("step", steps - 17), ("check",)]
+    ab = run(lbm, c, plan, lbm.PATTERN_AB)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    assert_same(ab, aa)
+    tr = aa[-1][3]
+    assert len(tr) > int(c.active_blocks.sum()) and aa[-1][2]["leak"] == 0
+    joined = tr[tr[:, 0] > 0, 0]
+    assert (joined % 2 == 0).any() and (joined % 2 == 1).any()  # both parities
+
+
+def test_progressive_equals_static_in_place(lbm):
+    """The progressive in-place run reproduces the static in-place run."""
+    c = W.porous_injection(64, seed=2)
+    plan = [("step", 75), ("check",)]
+    pg = run(lbm, c, plan, lbm.PATTERN_AA)
+    st = run(lbm, c, plan, lbm.PATTERN_AA, progressive=False)
+    assert pg[0][2]["leak"] == 0
+    for x, y in zip(pg[0][0][:3], st[0][0][:3]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_seam_droplet_in_place_vs_oracle(lbm, ncomp):
+    """Periodic-seam droplet: the mesh grows across the periodic faces; after
+    an odd step count the state sits at the neighbours' swapped addresses."""
+    c = W.droplet_seam(48, seed=0, ncomp=ncomp)
+    plan = [("step", 21), ("check",)]
+    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    ab = run(lbm, c, plan, lbm.PATTERN_AB)
+    assert_same(ab, aa)
+    ref = oracle.Sim(c.params, c.solid, c.rho0, c.u0, c.active_blocks)
+    ref.step(21)
+    rr, ur, _, _ = ref.moments()
+    rho, u = aa[0][0][0], aa[0][0][1]
+    for a in range(ncomp):
+        assert rel_linf(rho[a], rr[a]) <= 1e-5
+    assert rel_linf(u, ur) <= 1e-5
+    assert aa[0][2]["activations"] > 0 and aa[0][2]["leak"] == 0
+
+
+def test_caller_activation_between_steps(lbm):
+    """Blocks the caller activates between steps, after odd and after even
+    step counts, next to active blocks and away from them: the in-place run
+    still equals the two-buffer run with the same calls."""
+    c = W.porous_injection(64, seed=3)
+    nb = c.n_blocks
+    plan = [("step", 9), ("activate", np.array([1, 5, nb - 1])), ("check",), ("step", 10),
+            ("activate", np.array([2, 6, 17, nb // 2])), ("check",), ("step", 1), ("check",), ("step", 30),
+            ("check",)]
+    ab = run(lbm, c, plan, lbm.PATTERN_AB)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    assert_same(ab, aa)
+    assert aa[-1][2]["leak"] == 0
+
+
+def test_channels_in_place(lbm):
+    """Channel network (inlet, outlet, walls, sealed tubes never meshed)."""
+    c = W.channel_network(128, 64, 32, seed=1, n_live=2)
+    plan = [("step", 33), ("check",)]
+    ab = run(lbm, c, plan, lbm.PATTERN_AB)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    assert_same(ab, aa)
+
+
+def test_in_place_halves_population_memory(lbm):
+    """One population buffer instead of two, plus one psi plane per
+    component."""
+    c = W.porous_injection(64, seed=2)
+    s_ab = lbm.Simulation(c, pattern=lbm.PATTERN_AB)
+    s_aa = lbm.Simulation(c, pattern=lbm.PATTERN_AA)
+    try:
+        a, b = s_ab.stats(), s_aa.stats()
+        plane = (a["capacity"] + 1) * 4096
+        assert a["bytes_reserved"] - b["bytes_reserved"] == 4 * 2 * 19 * plane - 4 * 2 * plane
+        assert b["bytes_active"] < 0.6 * a["bytes_active"]
+    finally:
+        s_ab.close()
+        s_aa.close()
+
+
+def test_in_place_rejections(lbm):
+    from paper_1510_03560_amd import batch as B
+    from paper_1510_03560_amd import mlp as M
+    c = W.porous_injection(64, seed=2)
+    sim = lbm.Simulation(c, pattern=lbm.PATTERN_AA)
+    try:
+        with pytest.raises(lbm.LbmError) as ei:
+            M.set_proposal(sim, M.initial_params(0), 0.5)
+        assert ei.value.code == -1
+        with pytest.raises(Exception) as ei:
+            B.lbm_batch_create([sim.h])
+        assert "LBM_PATTERN_AA" in str(ei.value) or "EINVAL" in str(ei.value)
+        sim.step(3)  # still usable
+        assert sim.stats()["steps"] == 3
+    finally:
+        sim.close()
