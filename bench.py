@@ -142,6 +142,16 @@ def summarize_pmc(fetch_csv: str, write_csv: str, last: int) -> dict:
     sw = next(vs for k, vs in w.items() if STEP_KERNEL in k.replace("void ", ""))[-last:]
     fb = float(np.median(sf)) * 1024.0 * fetch_scale
     wb = float(np.median(sw)) * 1024.0 * write_scale
+    # the in-place pattern's kernels, when the run had them (median of the
+    # last launches of each instantiation)
+    inplace = {}
+    for k, vs in f.items():
+        if "k_inplace" in k and k in w:
+            inplace[_short(k)] = {
+                "launches": len(vs[-last:]),
+                "fetch_bytes_per_launch": float(np.median(vs[-last:])) * 1024.0 * fetch_scale,
+                "write_bytes_per_launch": float(np.median(w[k][-last:])) * 1024.0 * write_scale,
+            }
     return {
         "kernel": _short(STEP_KERNEL),
         "kernel_source_sha256": kernel_source_hash(),
@@ -152,6 +162,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, last: int) -> dict:
         "fetch_factor": fetch_scale, "write_factor": write_scale,
         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
         "fused_step_bytes_per_launch": fb + wb,
+        "inplace_kernels": inplace,
     }
 
 
