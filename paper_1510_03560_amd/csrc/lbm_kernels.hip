@@ -1441,12 +1441,18 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, B
         dst[i] = keep ? own_o : (second ? tcell + plane : tcell);
       }
     });
+    // even index: every line is written whole by one store of the wave,
+    // non-temporal; odd index: the shifted stores write parts of lines that
+    // other waves complete, which the L2 merges while it holds them
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       unroll<kQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-        st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
+        if constexpr (kOdd)
+          st(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
+        else
+          st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
       });
     }
   }

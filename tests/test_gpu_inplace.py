@@ -180,3 +180,34 @@ def test_in_place_rejections(lbm):
         assert sim.stats()["steps"] == 3
     finally:
         sim.close()
+
+
+def test_single_block_lattice_in_place(lbm):
+    """16^3 periodic droplet: one block, its own neighbour in every direction,
+    so odd-index steps stream into the block from its opposite faces."""
+    c = W.droplet_periodic(16, 4)
+    plan = [("step", 1), ("check",), ("step", 32), ("check",)]
+    assert_same(run(lbm, c, plan, lbm.PATTERN_AB), run(lbm, c, plan, lbm.PATTERN_AA))
+
+
+def test_empty_mesh_and_zero_steps_in_place(lbm):
+    c = W.droplet_periodic(32, 0)
+    rest = W.Case("rest", c.params, c.solid, None, None, np.zeros(c.n_blocks, np.uint8))
+    out = run(lbm, rest, [("check",), ("step", 0), ("step", 7), ("check",)], lbm.PATTERN_AA, progressive=True)
+    (m0, _, _, _), (m1, _, s1, _) = out
+    assert s1["n_active"] == 0 and s1["activations"] == 0 and s1["steps"] == 7
+    for x, y in zip(m0, m1):
+        assert np.array_equal(x, y)
+
+
+def test_porous_box_at_rest_stays_at_rest_in_place(lbm):
+    """Walls, an outlet and spheres, every cell at rest: the in-place update
+    leaves the rest state unchanged to the bit after both parities."""
+    c = W.porous_injection(64, seed=4)
+    rest_params = dict(c.params, bc=(W.WALL, W.OUTLET, W.WALL, W.WALL, W.WALL, W.WALL))
+    rest = W.Case("rest-box", rest_params, c.solid, None, None, None)
+    out = run(lbm, rest, [("check",), ("step", 1), ("check",), ("step", 1), ("check",)], lbm.PATTERN_AA,
+              progressive=False)
+    for k in (1, 2):
+        for x, y in zip(out[0][0][:3], out[k][0][:3]):
+            assert np.array_equal(x, y)
