@@ -176,6 +176,18 @@ def active_cells_per_step(trace: np.ndarray, n0: int, t0: int, k: int) -> np.nda
     return n
 
 
+def mesh_growth(trace: np.ndarray, stats: dict, total_steps: int) -> dict:
+    """Active blocks and the device bytes of their slots at sampled steps of
+    a progressive run, from its activation trace (the single-GPU analogue of
+    the paper's memory-over-time figures)."""
+    per_slot = stats["bytes_active"] / max(stats["n_active"], 1)
+    at = sorted({t for t in (0, 1, 2, 5, 10, 20, 30, 40, 50, 75, 100, 150, 200, 300, 500, 1000, 2000, 5000,
+                             total_steps) if t <= total_steps})
+    steps = trace[:, 0] if len(trace) else np.zeros(0, np.int32)
+    blocks = [int((steps <= t).sum()) for t in at]
+    return {"steps": at, "active_blocks": blocks, "bytes_active": [int(b * per_slot) for b in blocks]}
+
+
 def fluid_cells_of_active(case, trace, t) -> int:
     """Fluid cells in the blocks active during step t."""
     p = case.params
@@ -646,6 +658,7 @@ def main():
         "progressive_over_static_time": round(prog["ms"] / stat["ms"], 4),
         "static_active_cell_mlups": round(cells_full * K / (stat["ms"] * 1e-3) / 1e6, 2),
         "leak": int(prog["stats"]["leak"]),
+        "mesh_growth": mesh_growth(prog["trace"], prog["stats"], Wm + K),
         "kernel_ms_per_launch": {k: round(v[1] / max(v[0], 1), 5) for k, v in times.items()},
         "roofline": {
             "kernel": dominant,

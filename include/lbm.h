@@ -121,7 +121,7 @@ typedef struct lbm_stats {
   int64_t clamps;           /* cells whose Eq 6 radicand was negative (psi set to 0) */
   int32_t numeric_error;    /* nonzero once a density was non-positive or non-finite */
   int32_t pool_full;        /* nonzero if an activation did not fit the pool */
-  int64_t activations;      /* blocks activated after t = 0 */
+  int64_t activations;      /* blocks activated so far, by lbm_activate or the criterion (trace entries) */
 } lbm_stats_t;
 /* leak: number of (step, cell, direction) links in which an active cell
  * showed a non-solid cell of an inactive block a pseudo-potential other than

@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -76,3 +77,14 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() == h
     (fake / "lbm_kernels.hip").write_text(text + "\nint changed;\n")
     assert bench.kernel_source_hash() != h
+
+
+def test_mesh_growth_counts_blocks_by_activation_step():
+    """A trace entry (s, b) means block b takes part from step s on."""
+    tr = np.array([[0, 1], [0, 2], [3, 5], [10, 7], [10, 8], [60, 9]], np.int32)
+    g = bench.mesh_growth(tr, {"bytes_active": 600, "n_active": 6}, 100)
+    d = dict(zip(g["steps"], g["active_blocks"]))
+    assert d[0] == 2 and d[2] == 2 and d[5] == 3 and d[10] == 5 and d[50] == 5 and d[100] == 6
+    assert g["steps"][-1] == 100 and g["bytes_active"][-1] == 600
+    empty = bench.mesh_growth(np.zeros((0, 2), np.int32), {"bytes_active": 0, "n_active": 0}, 10)
+    assert empty["active_blocks"] == [0] * len(empty["steps"])
