@@ -449,6 +449,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-single-steps", type=int, default=1,
+                    help="steps of the single-thread oracle sample (0: skip)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--summarize-trace", metavar="CSV",
@@ -692,6 +694,20 @@ def main():
             "sample": f"{args.cpu_steps} steps of the same {n}^3 lattice on the static mesh "
                       f"({stat['stats']['n_active']} active blocks), FP64, OpenMP, {cpu_model()}",
         }
+        if args.cpu_single_steps > 0:
+            # the same oracle on one thread (a shorter sample)
+            oracle.set_threads(1)
+            ref1 = oracle.Sim(case.params, case.solid, None, None, None)
+            t = time.perf_counter()
+            ref1.step(args.cpu_single_steps)
+            dt1 = time.perf_counter() - t
+            oracle.set_threads(used)
+            res["cpu_single_thread"] = {
+                "value": round(cells_full * args.cpu_single_steps / dt1 / 1e6, 3),
+                "unit": "MLUPS",
+                "cores": 1,
+                "sample": f"{args.cpu_single_steps} steps of the same lattice, one thread",
+            }
     print(json.dumps(res), flush=True)
 
 
