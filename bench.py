@@ -44,6 +44,11 @@ K2_BYTES_PER_SOLID_CELL = 4
 # reads the populations (152 B) and the mask and writes psi (8 B).
 INPLACE_COLLIDE_BYTES_PER_FLUID_CELL = 2 * 19 * 4 * 2 + 4 + 8
 INPLACE_PSI_BYTES_PER_FLUID_CELL = 2 * 19 * 4 + 4 + 8
+# with the FP16-deviation store: populations at 2 B, plus the two reference
+# densities read and written by the collision pass (16 B) and read by the
+# psi pass (8 B)
+INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16 = 2 * 19 * 2 * 2 + 4 + 8 + 16
+INPLACE_PSI_BYTES_PER_FLUID_CELL_F16 = 2 * 19 * 2 + 4 + 8 + 8
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_porous192_traffic.json")
@@ -519,9 +524,6 @@ def main():
 
     store = lbm.STORE_F32 if args.store == "f32" else lbm.STORE_F16DEV
     pattern = lbm.PATTERN_AA if args.pattern == "aa" else lbm.PATTERN_AB
-    if pattern == lbm.PATTERN_AA and store != lbm.STORE_F32:
-        print("bench.py: the in-place pattern stores FP32 populations", file=sys.stderr)
-        sys.exit(2)
 
     def timed_run(progressive: bool):
         sim = lbm.Simulation(case, progressive=progressive, store=store, pattern=pattern)
@@ -568,7 +570,8 @@ def main():
     fluid_full = fluid_cells_of_active(case.static_twin(), np.zeros((0, 2), np.int32), 0)
     cells_full = stat["stats"]["n_active"] * 4096
     if pattern == lbm.PATTERN_AA:
-        per_fluid = INPLACE_COLLIDE_BYTES_PER_FLUID_CELL
+        per_fluid = (INPLACE_COLLIDE_BYTES_PER_FLUID_CELL if args.store == "f32"
+                     else INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16)
     else:
         per_fluid = K2_BYTES_PER_FLUID_CELL if args.store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
     k2_bytes = fluid_full * per_fluid + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
@@ -576,9 +579,9 @@ def main():
 
     # the in-place pattern on the same full mesh (half the population memory)
     inplace = None
-    if pattern == lbm.PATTERN_AB and args.store == "f32" and args.inplace_steps > 0:
+    if pattern == lbm.PATTERN_AB and args.inplace_steps > 0:
         Ki = args.inplace_steps
-        sim_a = lbm.Simulation(case, progressive=False, pattern=lbm.PATTERN_AA)
+        sim_a = lbm.Simulation(case, progressive=False, store=store, pattern=lbm.PATTERN_AA)
         sim_a.step(Wm)
         a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -595,9 +598,10 @@ def main():
         sim_a.close()
         col_ms = t_a["inplace_collide"][1] / max(t_a["inplace_collide"][0], 1)
         psi_ms = t_a["inplace_psi"][1] / max(t_a["inplace_psi"][0], 1)
-        col_bytes = (fluid_full * INPLACE_COLLIDE_BYTES_PER_FLUID_CELL
+        f32 = args.store == "f32"
+        col_bytes = (fluid_full * (INPLACE_COLLIDE_BYTES_PER_FLUID_CELL if f32 else INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16)
                      + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
-        psi_bytes = (fluid_full * INPLACE_PSI_BYTES_PER_FLUID_CELL
+        psi_bytes = (fluid_full * (INPLACE_PSI_BYTES_PER_FLUID_CELL if f32 else INPLACE_PSI_BYTES_PER_FLUID_CELL_F16)
                      + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
         inplace = {
             "steps": Ki,

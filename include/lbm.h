@@ -58,9 +58,9 @@ extern "C" {
  *   section 3, which halves the population memory): steps of even index
  *   read and write each cell's own populations with opposite directions
  *   swapped, steps of odd index read from and write to the neighbours.  Two
- *   kernels per step (psi, then collision and streaming).  FP32 store only;
- *   not with the learned proposal or in batches.  Results are bitwise those
- *   of LBM_PATTERN_AB. */
+ *   kernels per step (psi, then collision and streaming).  Either storage
+ *   format; not with the learned proposal or in batches.  Results are
+ *   bitwise those of LBM_PATTERN_AB with the same storage format. */
 #define LBM_PATTERN_AB 0
 #define LBM_PATTERN_AA 1
 

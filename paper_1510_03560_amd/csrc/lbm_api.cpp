@@ -181,8 +181,6 @@ int validate(const lbm_params* p) {
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
   if (p->pattern != LBM_PATTERN_AB && p->pattern != LBM_PATTERN_AA)
     return fail(nullptr, LBM_EINVAL, "pattern must be LBM_PATTERN_AB or LBM_PATTERN_AA");
-  if (p->pattern == LBM_PATTERN_AA && p->store != LBM_STORE_F32)
-    return fail(nullptr, LBM_EINVAL, "pattern LBM_PATTERN_AA needs store LBM_STORE_F32");
   for (int a = 0; a < p->ncomp; ++a) {
     if (!(p->tau[a] > 0.5)) return fail(nullptr, LBM_EINVAL, "tau[%d] must exceed 0.5 (got %g)", a, p->tau[a]);
     if (!(p->bg_rho[a] > 0.0)) return fail(nullptr, LBM_EINVAL, "bg_rho[%d] must be positive", a);
@@ -586,9 +584,9 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       if (rc) return rc;
     }
     if (aa) {
-      rc = timed(h, 5, [&] { return launch_inplace_psi(P, h->D, rd, h->stream); });
+      rc = timed(h, 5, [&] { return launch_inplace_psi(P, h->D, rb, rd, h->stream); });
       if (rc) return rc;
-      rc = timed(h, 6, [&] { return launch_inplace_collide(P, h->D, rd, h->stream); });
+      rc = timed(h, 6, [&] { return launch_inplace_collide(P, h->D, rb, rd, h->stream); });
       if (rc) return rc;
     } else {
       rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
@@ -600,7 +598,7 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       HIP_TRY(h, hipEventRecord(h->nact_ev, h->stream));
       h->nact_pending = true;
     }
-    if (!aa) h->rbuf ^= 1;
+    h->rbuf ^= 1;  // in place: both indices name the one population buffer
     h->step++;
   }
   return LBM_OK;

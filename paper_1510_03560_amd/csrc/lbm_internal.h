@@ -87,7 +87,8 @@ struct Params {
 // Device buffers of one handle.
 // A "plane" holds one value per cell of every slot: index slot*4096 + cell.
 struct Buffers {
-  void* f[2];             // populations: [ncomp*19 planes] of float or __half (in place: f[1] == f[0])
+  void* f[2];             // populations: [ncomp*19 planes] of float or __half (in place: f[1] == f[0],
+                          // and the buffer index only selects the reference densities)
   float* psi;             // in place only: [ncomp planes] pseudo-potential of the step being taken
   float* rho[2];          // FP16 store only: [ncomp planes] reference densities, double-buffered
   uint32_t* mask;         // [1 plane]: bit i = link i bounces; kind in bits 24..25
@@ -143,11 +144,12 @@ enum : int {
 };
 hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, int rd, int flags,
                             hipStream_t stream);
-// In-place step (one population buffer, FP32): psi of every cell of the
-// active blocks into D.psi, then forces, collision and streaming in place.
-// rd: kRdOwn for the first step, then kRdAAOdd / kRdAAEven by step parity.
-hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rd, hipStream_t stream);
-hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rd, hipStream_t stream);
+// In-place step (one population buffer): psi of every cell of the active
+// blocks into D.psi, then forces, collision and streaming in place.
+// rd: kRdOwn for the first step, then kRdAAOdd / kRdAAEven by step parity;
+// rbuf: the reference densities read (FP16 store; this step writes rbuf ^ 1).
+hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rbuf, int rd, hipStream_t stream);
+hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rbuf, int rd, hipStream_t stream);
 // Learned activation proposal: list the candidate blocks, then per candidate
 // gather its 12 features; with mlp != nullptr also run the network and request
 // the block when its probability exceeds thr, else write feat[cap][12] and

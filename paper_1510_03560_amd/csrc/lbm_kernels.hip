@@ -387,7 +387,6 @@ __host__ __device__ __forceinline__ void pull_axes_z(int z, PullAxes& a) {
 template <int RD, bool REF>
 __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t own, uint32_t m, uint32_t plane,
                                         const int* nslot, int rest, Sources<REF>& s) {
-  static_assert(!REF || RD == kRdOwn || RD == kRdPull, "the in-place pattern stores FP32 populations");
   s.fidx[0] = own;
   if constexpr (REF) s.ridx[0] = own;
   const uint32_t own_second = own + plane;
@@ -433,6 +432,8 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
         // the rest slot (which stores it swapped, like a post-collision cell)
         s.fidx[i] = (bounce || slot[i] != rest) ? own_i : src_o;
       }
+      // reference density (FP16 store): that of the cell that wrote the
+      // value, which is the source cell, or the cell itself for a bounced link
       if constexpr (REF) s.ridx[i] = bounce ? own : src_cell;
     });
   }
@@ -1290,8 +1291,8 @@ constexpr int kInplaceThreads = 256;
 // Pass 1: psi (Eq 6-7) of every cell of the active blocks (fluid cells from
 // their densities, inlet nodes psi(inlet density), outlet and solid cells the
 // rest value) into D.psi.
-template <int NC, int RD>
-__global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D) {
+template <typename S, int NC, int RD>
+__global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D, int rbuf) {
   const int n_active = D.ctrl[kNActive];
   const int g = slot_of_workgroup(blockIdx.x, n_active);
   if (g >= n_active) return;
@@ -1304,7 +1305,8 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D) {
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const uint32_t plane = P.plane;
-  const float* __restrict__ fb = static_cast<const float*>(D.f[0]);
+  const typename S::T* __restrict__ fb = fplane<S>(D, 0);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // references of f(t)
   const uint32_t own_base = (uint32_t)s * kCells;
   unsigned numeric = 0u, clamps = 0u;
 #pragma unroll 1
@@ -1316,13 +1318,13 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D) {
 #pragma unroll
     for (int a = 0; a < NC; ++a) psi[a] = kind == kInlet ? P.psi_in[a] : P.psi_rest[a];
     if (kind == kFluid) {
-      Sources<false> src;
+      Sources<S::kRef> src;
       pull_axes_z(z, pa);
-      sources<RD, false>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         float f[kQ];
-        gather<StoreF32>(fb, plane, a, src, nullptr, f);
+        gather<S>(fb, plane, a, src, rref, f);
         const float rho = moments(f).rho;
         bool cl;
         psi[a] = pseudo_potential(P, a, rho, cl);
@@ -1342,8 +1344,8 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D) {
 // active block; thread t owns column t of the block and sweeps z = 0 .. 15.
 // Inlet and outlet nodes stream their imposed state and solid cells write the
 // rest state to their own address, which nothing reads.
-template <int NC, int RD>
-__global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, Buffers D) {
+template <typename S, int NC, int RD>
+__global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, Buffers D, int rbuf) {
   static_assert(RD != kRdPull, "the in-place step reads in place");
   constexpr bool kOdd = RD == kRdAAOdd;
   const int n_active = D.ctrl[kNActive];
@@ -1365,7 +1367,10 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, B
   cell_xyz(t, cx, cy, cz0);
   const int hp = (cy + 1) * kH + (cx + 1);
   const uint32_t plane = P.plane;
-  float* __restrict__ fb = static_cast<float*>(D.f[0]);
+  using T = typename S::T;
+  T* __restrict__ fb = fplane<S>(D, 0);
+  const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // references of f(t)
+  float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;    // this step's densities
   const float* __restrict__ psi_g = D.psi;
   const uint32_t own_base = (uint32_t)s * kCells;
   // psi of footprint plane zp (x, y in [-1, 16]) into ring slot zp & 3;
@@ -1394,11 +1399,21 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, B
     const uint32_t kind = (m >> kKindShift) & 3u;
     pull_axes_z(z, pa);
     float fp[NC][kQ];
-    if (kind == kFluid) {
-      Sources<false> src;
-      sources<RD, false>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+    float rr[NC];  // FP16 store: the reference of what the cell writes, its density of this step
 #pragma unroll
-      for (int a = 0; a < NC; ++a) gather<StoreF32>(fb, plane, a, src, nullptr, fp[a]);
+    for (int a = 0; a < NC; ++a) rr[a] = P.rho_ref_rest[a];
+    // fluid cells, and (FP16 store) boundary nodes, whose density is the
+    // reference of what they write
+    if (kind == kFluid || (S::kRef && kind != kSolid)) {
+      Sources<S::kRef> src;
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        gather<S>(fb, plane, a, src, rref, fp[a]);
+        rr[a] = moments(fp[a]).rho;
+      }
+    }
+    if (kind == kFluid) {
       float psi_c[NC];
 #pragma unroll
       for (int a = 0; a < NC; ++a) psi_c[a] = psi_s[z & 3][a][hp];
@@ -1446,13 +1461,15 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, B
     // other waves complete, which the L2 merges while it holds them
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
+      if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
       unroll<kQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        const T enc = S::encode(fp[a][i], dir_w(i) * rr[a]);
         if constexpr (kOdd)
-          st(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
+          st(fb + (size_t)(a * kQ + first) * plane, dst[i] * (uint32_t)sizeof(T), enc);
         else
-          st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * 4u, fp[a][i]);
+          st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * (uint32_t)sizeof(T), enc);
       });
     }
   }
@@ -1968,10 +1985,8 @@ template <typename S, typename Fn>
 hipError_t with_rd(int rd, Fn&& fn) {
   if (rd == kRdOwn) return fn(std::integral_constant<int, kRdOwn>{});
   if (rd == kRdPull) return fn(std::integral_constant<int, kRdPull>{});
-  if constexpr (!S::kRef) {
-    if (rd == kRdAAEven) return fn(std::integral_constant<int, kRdAAEven>{});
-    if (rd == kRdAAOdd) return fn(std::integral_constant<int, kRdAAOdd>{});
-  }
+  if (rd == kRdAAEven) return fn(std::integral_constant<int, kRdAAEven>{});
+  if (rd == kRdAAOdd) return fn(std::integral_constant<int, kRdAAOdd>{});
   return hipErrorInvalidValue;
 }
 
@@ -2039,24 +2054,20 @@ struct CriterionL {
 };
 template <typename S, int NC>
 struct InplaceL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rd, bool collide_pass, hipStream_t st) {
-    if constexpr (S::kRef) {
-      return hipErrorInvalidValue;  // the in-place pattern stores FP32 populations
-    } else {
-      const dim3 g(grid_for(P.capacity));
-      return with_rd<S>(rd, [&](auto R) {
-        constexpr int M = decltype(R)::value;
-        if constexpr (M == kRdPull) {
-          return hipErrorInvalidValue;
-        } else {
-          if (collide_pass)
-            hipLaunchKernelGGL((k_inplace_collide<NC, M>), g, dim3(kInplaceThreads), 0, st, P, D);
-          else
-            hipLaunchKernelGGL((k_inplace_psi<NC, M>), g, dim3(kThreads), 0, st, P, D);
-          return hipGetLastError();
-        }
-      });
-    }
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, bool collide_pass, hipStream_t st) {
+    const dim3 g(grid_for(P.capacity));
+    return with_rd<S>(rd, [&](auto R) {
+      constexpr int M = decltype(R)::value;
+      if constexpr (M == kRdPull) {
+        return hipErrorInvalidValue;
+      } else {
+        if (collide_pass)
+          hipLaunchKernelGGL((k_inplace_collide<S, NC, M>), g, dim3(kInplaceThreads), 0, st, P, D, rbuf);
+        else
+          hipLaunchKernelGGL((k_inplace_psi<S, NC, M>), g, dim3(kThreads), 0, st, P, D, rbuf);
+        return hipGetLastError();
+      }
+    });
   }
 };
 template <typename S, int NC>
@@ -2160,12 +2171,12 @@ hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, int rd,
   return dispatch<CriterionL>(P, D, rbuf, rd, flags, stream);
 }
 
-hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rd, hipStream_t stream) {
-  return dispatch<InplaceL>(P, D, rd, false, stream);
+hipError_t launch_inplace_psi(const Params& P, const Buffers& D, int rbuf, int rd, hipStream_t stream) {
+  return dispatch<InplaceL>(P, D, rbuf, rd, false, stream);
 }
 
-hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rd, hipStream_t stream) {
-  return dispatch<InplaceL>(P, D, rd, true, stream);
+hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rbuf, int rd, hipStream_t stream) {
+  return dispatch<InplaceL>(P, D, rbuf, rd, true, stream);
 }
 
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream) {

@@ -102,15 +102,6 @@ def test_invalid_params_rejected_without_gpu(L, field, value, needle):
     assert needle in str(ei.value)
 
 
-def test_in_place_pattern_needs_fp32_store(L):
-    """The in-place pattern stores FP32 populations only; the check comes
-    before any device work."""
-    p = L.make_params(W.droplet_periodic(32, 0).params, store=L.STORE_F16DEV, pattern=L.PATTERN_AA)
-    with pytest.raises(L.LbmError) as ei:
-        L.lbm_create(p, stream=0)
-    assert ei.value.code == -1 and "LBM_STORE_F32" in str(ei.value)
-
-
 def test_kernel_names_cover_both_patterns(L):
     lib = L.load()
     names = [lib.lbm_kernel_name(k).decode() for k in range(L.NUM_KERNELS)]

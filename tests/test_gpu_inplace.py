@@ -3,8 +3,8 @@ updated in place (section 3).  Its kernels carry out the arithmetic of the
 two-buffer step in the same order, so every field must equal the two-buffer
 run to the bit, after odd and even step counts, on static and progressive
 meshes (blocks joining at both step parities, by the criterion and by the
-caller), with walls, inlet and outlet, one or two components; and the FP64
-oracle bounds both."""
+caller), with walls, inlet and outlet, one or two components, FP32 and
+FP16-deviation store; and the FP64 oracle bounds both."""
 import os
 
 import numpy as np
@@ -32,10 +32,10 @@ def rel_linf(a, b):
     return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
 
 
-def run(lbm, case, plan, pattern, progressive=None):
+def run(lbm, case, plan, pattern, progressive=None, store=0):
     """plan: list of ("step", n) / ("activate", block ids) / ("check",);
     returns the fields, psi/force dumps and stats at every check."""
-    sim = lbm.Simulation(case, progressive=progressive, pattern=pattern)
+    sim = lbm.Simulation(case, progressive=progressive, pattern=pattern, store=store)
     out = []
     try:
         for item in plan:
@@ -79,14 +79,15 @@ def test_static_droplet_equals_two_buffers_bitwise(lbm):
     assert rel_linf(u, ur) <= 1e-5
 
 
-@pytest.mark.parametrize("steps", [61, 80])
-def test_progressive_porous_equals_two_buffers_bitwise(lbm, steps):
+@pytest.mark.parametrize("steps,store", [(61, 0), (80, 0), (61, 1), (80, 1)])
+def test_progressive_porous_equals_two_buffers_bitwise(lbm, steps, store):
     """Porous injection at 64^3 (inlet, outlet, walls): the mesh grows from
-    the inlet blocks, blocks join after steps of both parities."""
+    the inlet blocks, blocks join after steps of both parities; FP32 and
+    FP16-deviation store."""
     c = W.porous_injection(64, seed=2)
     plan = [("step", 17), ("check",), ("step", steps - 17), ("check",)]
-    ab = run(lbm, c, plan, lbm.PATTERN_AB)
-    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    ab = run(lbm, c, plan, lbm.PATTERN_AB, store=store)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA, store=store)
     assert_same(ab, aa)
     tr = aa[-1][3]
     assert len(tr) > int(c.active_blocks.sum()) and aa[-1][2]["leak"] == 0
@@ -124,7 +125,8 @@ def test_seam_droplet_in_place_vs_oracle(lbm, ncomp):
     assert aa[0][2]["activations"] > 0 and aa[0][2]["leak"] == 0
 
 
-def test_caller_activation_between_steps(lbm):
+@pytest.mark.parametrize("store", [0, 1])
+def test_caller_activation_between_steps(lbm, store):
     """Blocks the caller activates between steps, after odd and after even
     step counts, next to active blocks and away from them: the in-place run
     still equals the two-buffer run with the same calls."""
@@ -133,8 +135,8 @@ def test_caller_activation_between_steps(lbm):
     plan = [("step", 9), ("activate", np.array([1, 5, nb - 1])), ("check",), ("step", 10),
             ("activate", np.array([2, 6, 17, nb // 2])), ("check",), ("step", 1), ("check",), ("step", 30),
             ("check",)]
-    ab = run(lbm, c, plan, lbm.PATTERN_AB)
-    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    ab = run(lbm, c, plan, lbm.PATTERN_AB, store=store)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA, store=store)
     assert_same(ab, aa)
     assert aa[-1][2]["leak"] == 0
 
@@ -165,6 +167,7 @@ def test_in_place_halves_population_memory(lbm):
 
 
 def test_in_place_rejections(lbm):
+    """The learned proposal and batches take two-buffer handles only."""
     from paper_1510_03560_amd import batch as B
     from paper_1510_03560_amd import mlp as M
     c = W.porous_injection(64, seed=2)
@@ -182,12 +185,13 @@ def test_in_place_rejections(lbm):
         sim.close()
 
 
-def test_single_block_lattice_in_place(lbm):
+@pytest.mark.parametrize("store", [0, 1])
+def test_single_block_lattice_in_place(lbm, store):
     """16^3 periodic droplet: one block, its own neighbour in every direction,
     so odd-index steps stream into the block from its opposite faces."""
     c = W.droplet_periodic(16, 4)
     plan = [("step", 1), ("check",), ("step", 32), ("check",)]
-    assert_same(run(lbm, c, plan, lbm.PATTERN_AB), run(lbm, c, plan, lbm.PATTERN_AA))
+    assert_same(run(lbm, c, plan, lbm.PATTERN_AB, store=store), run(lbm, c, plan, lbm.PATTERN_AA, store=store))
 
 
 def test_empty_mesh_and_zero_steps_in_place(lbm):
@@ -213,8 +217,8 @@ def test_porous_box_at_rest_stays_at_rest_in_place(lbm):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("variant", ["late", "thin"])
-def test_leaking_mesh_in_place_equals_two_buffers(lbm, variant):
+@pytest.mark.parametrize("variant,store", [("late", 0), ("thin", 0), ("late", 1)])
+def test_leaking_mesh_in_place_equals_two_buffers(lbm, variant, store):
     """A late criterion (S = 1e-3) or a one-cell shell lets the mesh miss
     populations: cells hand non-rest values to blocks that stay inactive.
     The in-place run keeps those values where the two-buffer run would have
@@ -225,8 +229,40 @@ def test_leaking_mesh_in_place_equals_two_buffers(lbm, variant):
     p = dict(case.params, S=1e-3) if variant == "late" else dict(case.params, shell_width=1)
     c = W.Case(variant, p, case.solid, None, None, case.active_blocks)
     plan = [("step", 45), ("check",), ("step", 16), ("check",)]
-    ab = run(lbm, c, plan, lbm.PATTERN_AB)
-    aa = run(lbm, c, plan, lbm.PATTERN_AA)
+    ab = run(lbm, c, plan, lbm.PATTERN_AB, store=store)
+    aa = run(lbm, c, plan, lbm.PATTERN_AA, store=store)
     assert_same(ab, aa)
     if variant == "late":
         assert aa[-1][2]["leak"] > 0
+
+
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_seam_droplet_in_place_f16_vs_oracle(lbm, ncomp):
+    """FP16-deviation store in place: bitwise the FP16 two-buffer run, and
+    within the FP16 bound of the oracle."""
+    c = W.droplet_seam(48, seed=0, ncomp=ncomp)
+    plan = [("step", 21), ("check",)]
+    aa = run(lbm, c, plan, lbm.PATTERN_AA, store=lbm.STORE_F16DEV)
+    ab = run(lbm, c, plan, lbm.PATTERN_AB, store=lbm.STORE_F16DEV)
+    assert_same(ab, aa)
+    ref = oracle.Sim(c.params, c.solid, c.rho0, c.u0, c.active_blocks)
+    ref.step(21)
+    rr, ur, _, _ = ref.moments()
+    for a in range(ncomp):
+        assert rel_linf(aa[0][0][0][a], rr[a]) <= 2e-3
+    assert rel_linf(aa[0][0][1], ur) <= 2e-3
+
+
+def test_in_place_f16_memory(lbm):
+    """FP16 store in place: one buffer of 2-byte populations; the reference
+    densities stay double-buffered."""
+    c = W.porous_injection(64, seed=2)
+    s_ab = lbm.Simulation(c, pattern=lbm.PATTERN_AB, store=lbm.STORE_F16DEV)
+    s_aa = lbm.Simulation(c, pattern=lbm.PATTERN_AA, store=lbm.STORE_F16DEV)
+    try:
+        a, b = s_ab.stats(), s_aa.stats()
+        plane = (a["capacity"] + 1) * 4096
+        assert a["bytes_reserved"] - b["bytes_reserved"] == 2 * 2 * 19 * plane - 4 * 2 * plane
+    finally:
+        s_ab.close()
+        s_aa.close()
