@@ -1276,7 +1276,10 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
 // overwritten, so the step runs as two passes: k_inplace_psi stores psi of
 // every cell of the active blocks, k_inplace_collide takes the forces from
 // it, collides and streams.  The arithmetic of each cell is that of k_fused,
-// in the same order, so both patterns give the same bits.
+// in the same order, so both patterns give the same bits.  With the
+// FP16-deviation store a value decodes with the density of the cell that
+// wrote it, which is the link's source in both parities (the cell itself for
+// a bounced link); those densities stay double-buffered by step parity.
 //
 // Progressive mesh: a link from a cell of an inactive block carries the rest
 // state.  At a step of odd index a population streamed towards a block that
