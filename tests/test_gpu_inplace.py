@@ -266,3 +266,20 @@ def test_in_place_f16_memory(lbm):
     finally:
         s_ab.close()
         s_aa.close()
+
+
+def test_choose_pattern(lbm):
+    """The pattern chooser times both patterns and respects a memory budget
+    (the in-place pattern is the only one that fits below the two-buffer
+    footprint)."""
+    from paper_1510_03560_amd import tune
+    c = W.porous_injection(64, seed=2)
+    r = tune.choose_pattern(c, steps=10, warmup=2)
+    t = {x["pattern"]: x for x in r["timings"]}
+    assert set(t) == {lbm.PATTERN_AB, lbm.PATTERN_AA}
+    assert r["pattern"] in t and all(x["ms_per_step"] > 0 for x in t.values())
+    assert t[r["pattern"]]["ms_per_step"] == min(x["ms_per_step"] for x in t.values())
+    cap = t[lbm.PATTERN_AB]["bytes_reserved"] - 1
+    assert tune.choose_pattern(c, steps=4, warmup=2, max_bytes=cap)["pattern"] == lbm.PATTERN_AA
+    with pytest.raises(ValueError):
+        tune.choose_pattern(c, steps=2, warmup=1, max_bytes=1000)
