@@ -55,8 +55,8 @@ int lbm_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t t
 
 /* Proposal features of the current state of a handle (progressive mesh):
  * for every inactive block holding fluid with at least one active
- * neighbour (a candidate), 12 values (see DESIGN of the proposal in
- * lbm_set_proposal) into feat[cap][12] and the block id into block[cap]
+ * neighbour (a candidate), 12 values (listed at lbm_set_proposal below)
+ * into feat[cap][12] and the block id into block[cap]
  * (device buffers).  Returns the number of candidates (may exceed cap; only
  * cap are written) or a negative error.  Synchronous. */
 int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap);

@@ -570,7 +570,7 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
         rc = timed(h, 4, [&] {
           hipError_t e = launch_candidates(P, h->D, h->stream);
           if (e == hipSuccess)
-            e = launch_propose(P, h->D, rb, pull, (int)h->step, h->mlp_dev, h->prop_thr, nullptr, nullptr, 0,
+            e = launch_propose(P, h->D, rb, rd, (int)h->step, h->mlp_dev, h->prop_thr, nullptr, nullptr, 0,
                                h->stream);
           return e;
         });
@@ -772,10 +772,9 @@ int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap) {
   if (!h) return LBM_EINVAL;
   if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_proposal_features before lbm_set_geometry");
   if (cap < 0 || (cap > 0 && (!feat || !block))) return fail(h, LBM_EINVAL, "bad feature buffers");
-  if (in_place(h)) return fail(h, LBM_EINVAL, "the proposal reads two-buffer (LBM_PATTERN_AB) handles only");
   hipError_t e = launch_candidates(h->P, h->D, h->stream);
   if (e == hipSuccess)
-    e = launch_propose(h->P, h->D, h->rbuf, h->step > 0, (int)h->step, nullptr, 0.0f, feat, block, cap, h->stream);
+    e = launch_propose(h->P, h->D, h->rbuf, read_mode(h), (int)h->step, nullptr, 0.0f, feat, block, cap, h->stream);
   if (e != hipSuccess) return fail(h, LBM_EHIP, "proposal features: %s", hipGetErrorString(e));
   int32_t ctrl[kNumCtrl];
   HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -791,7 +790,6 @@ int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t ena
   }
   if (!params) return fail(h, LBM_EINVAL, "proposal parameters missing");
   if (!h->user.progressive) return fail(h, LBM_EINVAL, "the proposal needs a progressive mesh");
-  if (in_place(h)) return fail(h, LBM_EINVAL, "the proposal reads two-buffer (LBM_PATTERN_AB) handles only");
   if (!h->mlp_dev) {
     h->mlp_dev = (float*)dev_alloc(h, sizeof(float) * LBM_MLP_NPARAMS);
     if (!h->mlp_dev) return fail(h, LBM_ENOMEM, "device allocation failed (proposal)");

@@ -155,7 +155,7 @@ hipError_t launch_inplace_collide(const Params& P, const Buffers& D, int rbuf, i
 // the block when its probability exceeds thr, else write feat[cap][12] and
 // block[cap] for the first cap candidates.
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream);
-hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, int rd, int step, const float* mlp,
                           float thr, float* feat, int32_t* block, int cap, hipStream_t stream);
 // Batched step: criterion (progressive), activation, initialisation,
 // merged list, fused step, step counters; `first` selects the first step

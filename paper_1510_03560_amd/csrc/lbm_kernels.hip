@@ -1700,7 +1700,7 @@ __global__ void __launch_bounds__(1024) k_candidates(Params P, Buffers D) {
 constexpr int kFeat = 12;
 constexpr int kPropThreads = 256;
 
-template <typename S, int NC, bool PULL>
+template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, int rbuf, int step,
                                                           const float* __restrict__ mlp, float thr,
                                                           float* __restrict__ feat_out,
@@ -1768,7 +1768,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
       pull_axes_xy(x, y, pa);
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
-      sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cid, m, plane, nslotB, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, nslotB, P.capacity, src);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         float f[kQ];
@@ -2075,14 +2075,14 @@ struct InplaceL {
 };
 template <typename S, int NC>
 struct ProposeL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, int rd, int step, const float* mlp,
                            float thr, float* feat, int32_t* block, int cap, hipStream_t st) {
     const dim3 g(P.nb > 0 ? P.nb : 1), b(kPropThreads);
-    if (pull)
-      hipLaunchKernelGGL((k_propose<S, NC, true>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
-    else
-      hipLaunchKernelGGL((k_propose<S, NC, false>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat, block, cap);
-    return hipGetLastError();
+    return with_rd<S>(rd, [&](auto R) {
+      hipLaunchKernelGGL((k_propose<S, NC, decltype(R)::value>), g, b, 0, st, P, D, rbuf, step, mlp, thr, feat,
+                         block, cap);
+      return hipGetLastError();
+    });
   }
 };
 // Batched stepping: prefix sums of the members' active counts (the merged
@@ -2198,9 +2198,9 @@ hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stre
   return hipGetLastError();
 }
 
-hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, bool pull, int step, const float* mlp,
+hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, int rd, int step, const float* mlp,
                           float thr, float* feat, int32_t* block, int cap, hipStream_t stream) {
-  return dispatch<ProposeL>(P, D, rbuf, pull, step, mlp, thr, feat, block, cap, stream);
+  return dispatch<ProposeL>(P, D, rbuf, rd, step, mlp, thr, feat, block, cap, stream);
 }
 
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u, float* umix,

@@ -167,15 +167,11 @@ def test_in_place_halves_population_memory(lbm):
 
 
 def test_in_place_rejections(lbm):
-    """The learned proposal and batches take two-buffer handles only."""
+    """Batches take two-buffer handles only."""
     from paper_1510_03560_amd import batch as B
-    from paper_1510_03560_amd import mlp as M
     c = W.porous_injection(64, seed=2)
     sim = lbm.Simulation(c, pattern=lbm.PATTERN_AA)
     try:
-        with pytest.raises(lbm.LbmError) as ei:
-            M.set_proposal(sim, M.initial_params(0), 0.5)
-        assert ei.value.code == -1
         with pytest.raises(Exception) as ei:
             B.lbm_batch_create([sim.h])
         assert "LBM_PATTERN_AA" in str(ei.value) or "EINVAL" in str(ei.value)
@@ -183,6 +179,33 @@ def test_in_place_rejections(lbm):
         assert sim.stats()["steps"] == 3
     finally:
         sim.close()
+
+
+def test_proposal_on_in_place_handle(lbm):
+    """The learned proposal reads the in-place state like the two-buffer one:
+    with the proposal on (random network, threshold 0.3, so that it requests
+    blocks), features, fields, trace and counters equal the two-buffer run."""
+    from paper_1510_03560_amd import mlp as M
+    c = W.porous_injection(64, seed=5)
+    params = M.initial_params(3)
+    out = {}
+    for pat in (lbm.PATTERN_AB, lbm.PATTERN_AA):
+        sim = lbm.Simulation(c, pattern=pat)
+        try:
+            M.set_proposal(sim, params, 0.3)
+            sim.step(23)
+            f1 = M.proposal_features(sim)
+            sim.step(14)
+            out[pat] = (sim.moments(), sim.stats(), sim.trace(), f1)
+        finally:
+            sim.close()
+    (m1, s1, t1, f1), (m2, s2, t2, f2) = out[lbm.PATTERN_AB], out[lbm.PATTERN_AA]
+    for x, y in zip(m1, m2):
+        assert np.array_equal(x, y)
+    assert np.array_equal(t1, t2) and s1["leak"] == s2["leak"] == 0
+    for x, y in zip(f1, f2):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    assert s2["activations"] > int(c.active_blocks.sum())
 
 
 @pytest.mark.parametrize("store", [0, 1])
