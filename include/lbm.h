@@ -59,8 +59,8 @@ extern "C" {
  *   read and write each cell's own populations with opposite directions
  *   swapped, steps of odd index read from and write to the neighbours.  Two
  *   kernels per step (psi, then collision and streaming).  Either storage
- *   format; not in batches (lbm_batch.h).  Results are bitwise those of
- *   LBM_PATTERN_AB with the same storage format. */
+ *   format.  Results are bitwise those of LBM_PATTERN_AB with the same
+ *   storage format. */
 #define LBM_PATTERN_AB 0
 #define LBM_PATTERN_AA 1
 

@@ -9,7 +9,7 @@
  * Members are existing handles (lbm.h) after lbm_set_geometry (and, for a
  * progressive mesh, after their first blocks were activated).  They must
  * share the storage format, the number of components, the mesh mode
- * (static or progressive) and their step count; the batch keeps pointers to
+ * (static or progressive), the access pattern and their step count; the batch keeps pointers to
  * them, so they must outlive it.  While a batch steps, the members are
  * ordered after the work already queued on their own streams, and work
  * queued on their streams afterwards waits for the batch.  Members can still

@@ -810,6 +810,7 @@ struct lbm_batch {
   Buffers* D_dev = nullptr;
   int32_t* off_dev = nullptr;
   bool progressive = false;
+  bool in_place = false;                          // members use LBM_PATTERN_AA
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
 };
 
@@ -828,9 +829,9 @@ int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
     lbm_t* h = hs[i];
     if (!h) return fail(nullptr, LBM_EINVAL, "batch: member %d is NULL", i);
     if (!h->geometry) return fail(nullptr, LBM_ESTATE, "batch: member %d has no geometry", i);
-    if (in_place(h)) return fail(nullptr, LBM_EINVAL, "batch: member %d uses LBM_PATTERN_AA (batches step A-B handles)", i);
-    if (h->P.store != h0->P.store || h->P.ncomp != h0->P.ncomp || h->user.progressive != h0->user.progressive)
-      return fail(nullptr, LBM_EINVAL, "batch: member %d differs in store, ncomp or mesh mode", i);
+    if (h->P.store != h0->P.store || h->P.ncomp != h0->P.ncomp || h->user.progressive != h0->user.progressive ||
+        h->user.pattern != h0->user.pattern)
+      return fail(nullptr, LBM_EINVAL, "batch: member %d differs in store, ncomp, mesh mode or pattern", i);
     if (h->step != h0->step || h->rbuf != h0->rbuf)
       return fail(nullptr, LBM_EINVAL, "batch: member %d is at another step", i);
     if (h->prop_enabled) return fail(nullptr, LBM_EINVAL, "batch: member %d has the proposal enabled", i);
@@ -838,6 +839,7 @@ int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
   lbm_batch* b = new lbm_batch();
   b->members.assign(hs, hs + n);
   b->progressive = h0->user.progressive != 0;
+  b->in_place = in_place(h0);
   std::vector<Params> P(n);
   std::vector<Buffers> D(n);
   int total = 0;
@@ -886,7 +888,7 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
   int rbuf = h0->rbuf;
   int32_t k = 0;
   auto eager = [&](bool first) {
-    const hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->stream);
+    const hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->in_place, b->stream);
     if (r == hipSuccess) {
       rbuf ^= 1;
       step++;
@@ -900,8 +902,8 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
     if (!g) {
       hipGraph_t graph = nullptr;
       e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->stream);
-      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->stream);
+      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->in_place, b->stream);
+      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->in_place, b->stream);
       hipError_t ec = hipStreamEndCapture(b->stream, &graph);
       if (e == hipSuccess) e = ec;
       if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);

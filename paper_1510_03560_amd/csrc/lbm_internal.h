@@ -163,7 +163,7 @@ hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, int rd, i
 // component count, mode and step parity.
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream);
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             hipStream_t stream);
+                             bool in_place, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, int rd, double* out2,

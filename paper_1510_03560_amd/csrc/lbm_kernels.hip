@@ -648,6 +648,7 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
   const Buffers& D = batched ? Bt.D[blockIdx.y] : Dv;
   const int first = from_dev ? D.ctrl[kNewFirst] : first_h;
   const int count = from_dev ? D.ctrl[kNewCount] : count_h;
+  if (batched) born = D.ctrl[kStepCount];  // the members' step, kept on the device
   const uint32_t plane = P.plane;
   typename S::T* fb = fplane<S>(D, buf);
   const long long N = (long long)P.nx * P.ny * P.nz;
@@ -1291,14 +1292,34 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
 
 constexpr int kInplaceThreads = 256;
 
+// The block of this workgroup: (simulation, position g in its active list in
+// block order); false for workgroups past the end of the list.
+template <bool BATCH>
+__device__ __forceinline__ bool workgroup_block(const Buffers& Dv, const Batch& Bt, int& sim, int& g) {
+  sim = 0;
+  if constexpr (BATCH) {
+    const int total = Bt.off[Bt.nsims];
+    const int gi = slot_of_workgroup(blockIdx.x, total);
+    if (gi >= total) return false;
+    sim = batch_sim(Bt, gi);
+    g = gi - Bt.off[sim];
+  } else {
+    const int n_active = Dv.ctrl[kNActive];
+    g = slot_of_workgroup(blockIdx.x, n_active);
+    if (g >= n_active) return false;
+  }
+  return true;
+}
+
 // Pass 1: psi (Eq 6-7) of every cell of the active blocks (fluid cells from
 // their densities, inlet nodes psi(inlet density), outlet and solid cells the
 // rest value) into D.psi.
-template <typename S, int NC, int RD>
-__global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D, int rbuf) {
-  const int n_active = D.ctrl[kNActive];
-  const int g = slot_of_workgroup(blockIdx.x, n_active);
-  if (g >= n_active) return;
+template <typename S, int NC, int RD, bool BATCH>
+__global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv, int rbuf, Batch Bt) {
+  int sim, g;
+  if (!workgroup_block<BATCH>(Dv, Bt, sim, g)) return;
+  const Params& P = BATCH ? Bt.P[sim] : Pv;
+  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
   const int s = D.order[g];
   __shared__ BlockCtx ctx;
   setup_block(P, D, D.slot_block[s], ctx);
@@ -1347,13 +1368,14 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params P, Buffers D, i
 // active block; thread t owns column t of the block and sweeps z = 0 .. 15.
 // Inlet and outlet nodes stream their imposed state and solid cells write the
 // rest state to their own address, which nothing reads.
-template <typename S, int NC, int RD>
-__global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params P, Buffers D, int rbuf) {
+template <typename S, int NC, int RD, bool BATCH>
+__global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, Buffers Dv, int rbuf, Batch Bt) {
   static_assert(RD != kRdPull, "the in-place step reads in place");
   constexpr bool kOdd = RD == kRdAAOdd;
-  const int n_active = D.ctrl[kNActive];
-  const int g = slot_of_workgroup(blockIdx.x, n_active);
-  if (g >= n_active) return;
+  int sim, g;
+  if (!workgroup_block<BATCH>(Dv, Bt, sim, g)) return;
+  const Params& P = BATCH ? Bt.P[sim] : Pv;
+  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
   const int s = D.order[g];
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
@@ -2065,9 +2087,10 @@ struct InplaceL {
         return hipErrorInvalidValue;
       } else {
         if (collide_pass)
-          hipLaunchKernelGGL((k_inplace_collide<S, NC, M>), g, dim3(kInplaceThreads), 0, st, P, D, rbuf);
+          hipLaunchKernelGGL((k_inplace_collide<S, NC, M, false>), g, dim3(kInplaceThreads), 0, st, P, D, rbuf,
+                             Batch{});
         else
-          hipLaunchKernelGGL((k_inplace_psi<S, NC, M>), g, dim3(kThreads), 0, st, P, D, rbuf);
+          hipLaunchKernelGGL((k_inplace_psi<S, NC, M, false>), g, dim3(kThreads), 0, st, P, D, rbuf, Batch{});
         return hipGetLastError();
       }
     });
@@ -2103,8 +2126,34 @@ __global__ void k_batch_tick(Batch B) {
 template <typename S, int NC>
 struct BatchL {
   static hipError_t launch(const Params& P0, const Batch& B, int rbuf, bool first, bool progressive,
-                           hipStream_t st) {
+                           bool in_place, hipStream_t st) {
     const dim3 gc(grid_for(B.total_capacity)), bc(kThreads), gf(grid_for(B.total_capacity)), bf(kFusedThreads);
+    if (in_place) {
+      // the step's index has the parity of rbuf (both flip every step)
+      const int rd = first ? kRdOwn : (rbuf ? kRdAAOdd : kRdAAEven);
+      const int mode = first ? kInitNatural : (rbuf ? kInitSwapped : kInitStash);
+      return with_rd<S>(rd, [&](auto R) {
+        constexpr int M = decltype(R)::value;
+        if constexpr (M == kRdPull) {
+          return hipErrorInvalidValue;
+        } else {
+          if (progressive) {
+            const int flags = first ? (kCritRecord | kCritExposure)
+                                    : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
+            hipLaunchKernelGGL((k_criterion<S, NC, M, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
+            hipLaunchKernelGGL((k_activate<true>), dim3(B.nsims), dim3(1024), 0, st, P0, Buffers{}, 0, B);
+            hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
+                               mode, -1);
+            hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
+          }
+          hipLaunchKernelGGL((k_inplace_psi<S, NC, M, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, B);
+          hipLaunchKernelGGL((k_inplace_collide<S, NC, M, true>), gc, dim3(kInplaceThreads), 0, st, P0, Buffers{},
+                             rbuf, B);
+          hipLaunchKernelGGL(k_batch_tick, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B);
+          return hipGetLastError();
+        }
+      });
+    }
     if (progressive) {
       const int flags = first ? (kCritRecord | kCritExposure)
                               : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
@@ -2189,8 +2238,8 @@ hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t st
 }
 
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             hipStream_t stream) {
-  return dispatch<BatchL>(P0, B, rbuf, first, progressive, stream);
+                             bool in_place, hipStream_t stream) {
+  return dispatch<BatchL>(P0, B, rbuf, first, progressive, in_place, stream);
 }
 
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream) {

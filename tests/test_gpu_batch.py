@@ -45,10 +45,10 @@ def assert_same(a, b, tag):
     assert a["counters"] == b["counters"], f"{tag}: {a['counters']} != {b['counters']}"
 
 
-def run_alone(lbm, cases, schedule, store):
+def run_alone(lbm, cases, schedule, store, pattern=0):
     out = []
     for c in cases:
-        sim = lbm.Simulation(c, store=store)
+        sim = lbm.Simulation(c, store=store, pattern=pattern)
         for kind, n in schedule:
             sim.step(n)
         out.append(snapshot(sim))
@@ -56,9 +56,9 @@ def run_alone(lbm, cases, schedule, store):
     return out
 
 
-def run_batched(lbm, cases, schedule, store, use_graph):
+def run_batched(lbm, cases, schedule, store, use_graph, pattern=0):
     from paper_1510_03560_amd import batch
-    sims = [lbm.Simulation(c, store=store) for c in cases]
+    sims = [lbm.Simulation(c, store=store, pattern=pattern) for c in cases]
     b = batch.Batch(sims)
     for kind, n in schedule:
         if kind == "batch":
@@ -149,3 +149,34 @@ def test_batch_rejects_mixed_members(lbm):
     b.close()
     for x in (a, s, a2, a3):
         x.close()
+
+
+@pytest.mark.parametrize("use_graph,store,mesh", [(True, 0, "progressive"), (False, 0, "progressive"),
+                                                  (True, 1, "progressive"), (True, 0, "static")])
+def test_batch_in_place_matches_alone(lbm, use_graph, store, mesh):
+    """Members with one population buffer updated in place: the batch runs
+    the in-place kernels over the merged list, with the step parity captured
+    in its two graphs, and every member ends as if stepped alone (and as the
+    two-buffer batch)."""
+    cases = progressive_cases()[:4] if mesh == "progressive" else static_cases()
+    schedule = [("batch", 31), ("alone", 3), ("batch", 26)]
+    ref = run_alone(lbm, cases, schedule, store, pattern=lbm.PATTERN_AA)
+    got = run_batched(lbm, cases, schedule, store, use_graph, pattern=lbm.PATTERN_AA)
+    two = run_batched(lbm, cases, schedule, store, use_graph, pattern=lbm.PATTERN_AB)
+    for k, (a, b, c) in enumerate(zip(ref, got, two)):
+        assert_same(a, b, f"member {k}")
+        assert_same(c, b, f"member {k} vs two buffers")
+
+
+def test_batch_rejects_mixed_patterns(lbm):
+    from paper_1510_03560_amd import batch
+    c = progressive_cases()[0]
+    a = lbm.Simulation(c, pattern=lbm.PATTERN_AB)
+    b = lbm.Simulation(c, pattern=lbm.PATTERN_AA)
+    try:
+        with pytest.raises(Exception) as ei:
+            batch.lbm_batch_create([a.h, b.h])
+        assert "pattern" in str(ei.value) or "EINVAL" in str(ei.value)
+    finally:
+        a.close()
+        b.close()

@@ -166,21 +166,6 @@ def test_in_place_halves_population_memory(lbm):
         s_aa.close()
 
 
-def test_in_place_rejections(lbm):
-    """Batches take two-buffer handles only."""
-    from paper_1510_03560_amd import batch as B
-    c = W.porous_injection(64, seed=2)
-    sim = lbm.Simulation(c, pattern=lbm.PATTERN_AA)
-    try:
-        with pytest.raises(Exception) as ei:
-            B.lbm_batch_create([sim.h])
-        assert "LBM_PATTERN_AA" in str(ei.value) or "EINVAL" in str(ei.value)
-        sim.step(3)  # still usable
-        assert sim.stats()["steps"] == 3
-    finally:
-        sim.close()
-
-
 def test_proposal_on_in_place_handle(lbm):
     """The learned proposal reads the in-place state like the two-buffer one:
     with the proposal on (random network, threshold 0.3, so that it requests
