@@ -291,3 +291,27 @@ def test_choose_pattern(lbm):
     assert tune.choose_pattern(c, steps=4, warmup=2, max_bytes=cap)["pattern"] == lbm.PATTERN_AA
     with pytest.raises(ValueError):
         tune.choose_pattern(c, steps=2, warmup=1, max_bytes=1000)
+
+
+def test_benchmark_configuration_in_place_equals_two_buffers(lbm):
+    """The 192^3 porous-injection benchmark configuration, progressive, 121
+    steps (the mesh grows from 144 to several hundred blocks, joining after
+    steps of both parities): the in-place run equals the two-buffer run bit
+    for bit, trace and counters included."""
+    c = W.porous_injection(192, seed=0)
+    out = {}
+    for pat in (lbm.PATTERN_AB, lbm.PATTERN_AA):
+        sim = lbm.Simulation(c, pattern=pat)
+        try:
+            sim.step(121)
+            rho, u, _, act = sim.moments()
+            out[pat] = (rho, u, act, sim.stats(), sim.trace())
+        finally:
+            sim.close()
+    a, b = out[lbm.PATTERN_AB], out[lbm.PATTERN_AA]
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a[4], b[4])
+    for k in ("n_active", "leak", "clamps", "activations", "numeric_error"):
+        assert a[3][k] == b[3][k], k
+    assert b[3]["leak"] == 0 and b[3]["n_active"] > 144
