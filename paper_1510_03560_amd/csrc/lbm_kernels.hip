@@ -1398,15 +1398,20 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
   float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;    // this step's densities
   const float* __restrict__ psi_g = D.psi;
   const uint32_t own_base = (uint32_t)s * kCells;
-  // psi of footprint plane zp (x, y in [-1, 16]) into ring slot zp & 3;
-  // inactive neighbours read the rest slot, which holds psi_rest
+  // FP16 store: the references of f(t) over the same footprint (a link's
+  // value decodes with its source cell's), in a ring of their own
+  __shared__ float rref_s[S::kRef ? kPsiRing : 1][NC][S::kRef ? kFoot : 1];
+  // psi (and references) of footprint plane zp (x, y in [-1, 16]) into ring
+  // slot zp & 3; inactive neighbours read the rest slot, which holds psi_rest
+  // and the rest state's reference
   auto psi_load = [&](int zp) {
     for (int e = t; e < NC * kFoot; e += kInplaceThreads) {
       const int a = e / kFoot, col = e % kFoot;
       const int hx = col % kH - 1, hy = col / kH - 1;
       const int slot = ctx.nslot[13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(zp)];
-      psi_s[zp & 3][a][col] =
-          ld(psi_g + (size_t)a * plane, ((uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u);
+      const uint32_t off = ((uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u;
+      psi_s[zp & 3][a][col] = ld(psi_g + (size_t)a * plane, off);
+      if constexpr (S::kRef) rref_s[zp & 3][a][col] = ld(rref + (size_t)a * plane, off);
     }
   };
   psi_load(-1);
@@ -1434,7 +1439,20 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        gather<S>(fb, plane, a, src, rref, fp[a]);
+        if constexpr (S::kRef) {
+          // the source cell's reference, or the cell's own for a bounced
+          // link (and on the first step, which reads in place)
+          gather_ref<S>(fb, plane, a, src,
+                        [&](auto I) {
+                          constexpr int i = decltype(I)::value;
+                          const bool self = RD == kRdOwn || i == 0 || ((m >> i) & 1u);
+                          return self ? rref_s[z & 3][a][hp]
+                                      : rref_s[(z - dir_ez(i)) & 3][a][hp - dir_ex(i) - kH * dir_ey(i)];
+                        },
+                        fp[a]);
+        } else {
+          gather<S>(fb, plane, a, src, rref, fp[a]);
+        }
         rr[a] = moments(fp[a]).rho;
       }
     }
