@@ -645,7 +645,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.store == "f32" else "f32-compute/f16-store",
         "data": "synthetic",
         "config": {
             "workload": f"porous injection {n}^3, 16^3 blocks, spheres r 4-12, porosity "

@@ -10,7 +10,10 @@
  * Conventions for every call:
  *  - Lattice arrays on the host are indexed n = x + nx*(y + ny*z) (x fastest).
  *  - Block b covers cells [16*bx, 16*bx+16) x ... with b = bx + nbx*(by + nby*bz),
- *    nbx = nx/16 etc.
+ *    nbx = ceil(nx/16) etc.  A non-periodic axis whose length is not a
+ *    multiple of 16 is padded to whole blocks with solid cells, which act as
+ *    the walls of that face would (bounce-back, and the neutral neighbour of
+ *    Eq 8-9); host arrays keep the unpadded size.
  *  - All pointers in this header are HOST pointers unless stated otherwise.
  *    The caller owns them; the library copies what it needs during the call
  *    and keeps no pointer.
@@ -80,14 +83,16 @@ extern "C" {
  * velocity by more than S (Eq 13) between two steps, for any component.
  */
 typedef struct lbm_params {
-  int32_t nx, ny, nz;    /* lattice size; each a positive multiple of block */
+  int32_t nx, ny, nz;    /* lattice size; a periodic axis must be a multiple of block, other axes are padded */
   int32_t block;         /* block edge; must be 16 */
   int32_t ncomp;         /* number of components, 1 or 2 */
   int32_t shell_width;   /* criterion shell depth in cells, 1..8 (default 2) */
   int32_t bc[6];         /* LBM_BC_* per face; opposite faces must both be periodic or neither */
   int32_t store;         /* LBM_STORE_* */
   int32_t progressive;   /* 0: static mesh (every block holding fluid active); 1: progressive */
-  int32_t pool_blocks;   /* block slots to reserve; 0 = number of blocks holding fluid */
+  int32_t pool_blocks;   /* block slots to reserve; 0 = number of blocks holding fluid.  At most
+                            131071 with LBM_STORE_F32 and 262143 with LBM_STORE_F16DEV (the kernels
+                            address a pair of population planes with 32-bit byte offsets) */
   int32_t pattern;       /* LBM_PATTERN_* */
   double tau[2];         /* > 0.5 */
   double eos_a, eos_b, eos_R, eos_omega, T_over_Tc;
@@ -148,8 +153,19 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
  * and whose u0 is zero starts at the rest state; every other cell is at rest.
  * Static mesh: every block holding fluid is activated here.  Progressive
  * mesh: no block is active until lbm_activate.  Reserves the block pool.
- * Errors: LBM_ESTATE if called twice, LBM_ENOMEM, LBM_EHIP. */
+ * Errors: LBM_ESTATE if called twice, LBM_EINVAL if the pool would need more
+ * slots than the store can address (see pool_blocks), LBM_ENOMEM, LBM_EHIP. */
 int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const double* u0);
+
+/* Device bytes that lbm_create followed by lbm_set_geometry(solid) would hold
+ * for these parameters (the block pool sized as lbm_set_geometry sizes it),
+ * written to *bytes, without touching the device: for choosing a storage
+ * format or access pattern that fits a memory budget.  The initial fields of
+ * lbm_set_geometry (4*ncomp*N bytes, plus 12*N with velocities) come on top
+ * until the first step.  solid: N bytes as in lbm_set_geometry (NULL: no
+ * solid).  Errors: LBM_EINVAL (invalid parameters, as lbm_create, or a pool
+ * beyond the addressable slots); lbm_last_error(NULL) has the text. */
+int lbm_plan_bytes(const lbm_params* p, const uint8_t* solid, int64_t* bytes);
 
 /* Activates blocks (the "first sub-domain" of section 4.1, or any block a
  * caller wants meshed early).  block_ids: n block indices.  Blocks holding no

@@ -30,7 +30,8 @@ typedef struct lbm_batch lbm_batch_t;
 
 /* Creates a batch of n >= 1 handles (the handle array is copied).  The
  * learned proposal (lbm_mlp.h) must be disabled on every member.  Errors:
- * LBM_EINVAL (mismatched members, a member with the proposal enabled, NULL),
+ * LBM_EINVAL (mismatched members, a member with the proposal enabled, the
+ * same handle twice, NULL),
  * LBM_ESTATE (a member without geometry), LBM_EHIP (device allocation). */
 int lbm_batch_create(lbm_t* const* handles, int32_t n, lbm_batch_t** out);
 

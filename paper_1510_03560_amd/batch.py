@@ -48,6 +48,8 @@ class Batch:
 
     def __init__(self, sims):
         self.sims = list(sims)
+        if len({id(s) for s in self.sims}) != len(self.sims):
+            raise ValueError("a simulation appears twice in the batch")
         self.b = lbm_batch_create([s.h for s in self.sims])
 
     def step(self, n: int = 1, use_graph: bool = True):

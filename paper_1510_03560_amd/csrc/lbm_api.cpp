@@ -159,14 +159,111 @@ const int kEz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 
 
 double w_host(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// Non-periodic axes whose length is not a multiple of the block edge are
+// rounded up to whole blocks; the padding cells are solid (section 8(c)
+// reading of uneven edges: walls).
+int padded(int n) { return (n + kB - 1) / kB * kB; }
+
+// Largest pool the kernels can address.  They form 32-bit byte offsets within
+// the two planes of an opposite-direction pair (2 * plane * sizeof(population))
+// and within one mask, density or psi plane (4 * plane), with plane =
+// (slots + 1) * 4096 cells: the pool must keep both below 2^32.
+int max_slots(int store) {
+  const uint64_t lim = (uint64_t)1 << 32;
+  const uint64_t fsz = store == LBM_STORE_F16DEV ? 2 : 4;
+  const uint64_t per_slot = (uint64_t)kCells * (2 * fsz > 4 ? 2 * fsz : 4);
+  return (int)(lim / per_slot) - 1;
+}
+
+// Device bytes of the buffers lbm_set_geometry reserves (each as dev_alloc
+// rounds it), for a pool of cap slots over nb blocks and N cells.
+struct GeometryLayout {
+  size_t f, psi, rho, mask, uprev, per_block_i32, per_block_u8, per_slot_i32, solid, trace, init_rho, init_u;
+  int64_t slot_bytes;  // bytes of one active block's slot
+  int64_t total(const lbm_params& u) const {
+    const bool aa = u.pattern == LBM_PATTERN_AA, f16 = u.store == LBM_STORE_F16DEV;
+    return (int64_t)((aa ? 1 : 2) * f + (aa ? psi : 0) + (f16 ? 2 * rho : 0) + mask + (u.progressive ? uprev : 0) +
+                     6 * per_block_i32 + per_block_u8 + 2 * per_slot_i32 + solid + trace);
+  }
+};
+
+size_t at_least_4(size_t b) { return b == 0 ? 4 : b; }
+
+GeometryLayout geometry_layout(const lbm_params& u, int cap, int nb, int64_t N) {
+  const size_t plane = (size_t)(cap + 1) * kCells;
+  const size_t fsz = u.store == LBM_STORE_F16DEV ? 2 : 4;
+  const bool f16 = u.store == LBM_STORE_F16DEV, aa = u.pattern == LBM_PATTERN_AA;
+  GeometryLayout L;
+  L.f = at_least_4(fsz * u.ncomp * kQ * plane);
+  L.psi = at_least_4(sizeof(float) * u.ncomp * plane);
+  L.rho = L.psi;
+  L.mask = at_least_4(sizeof(uint32_t) * plane);
+  L.uprev = at_least_4(sizeof(float) * u.ncomp * 3 * plane);
+  L.per_block_i32 = at_least_4(sizeof(int32_t) * (size_t)nb);
+  L.per_block_u8 = at_least_4((size_t)nb);
+  L.per_slot_i32 = at_least_4(sizeof(int32_t) * (size_t)cap);
+  L.solid = at_least_4((size_t)N);
+  L.trace = at_least_4(sizeof(int32_t) * 2 * (size_t)kTraceCap);
+  L.init_rho = at_least_4(sizeof(float) * u.ncomp * (size_t)N);
+  L.init_u = at_least_4(sizeof(float) * 3 * (size_t)N);
+  L.slot_bytes = (int64_t)kCells * ((int64_t)(aa ? 1 : 2) * fsz * u.ncomp * kQ + (f16 ? 8 * u.ncomp : 0) +
+                                    (aa ? 4 * u.ncomp : 0) + 4 + (u.progressive ? 12 * u.ncomp : 0));
+  return L;
+}
+
+// Per block of the padded block grid: holds a non-solid cell, holds an inlet
+// node, fraction of its 4096 cells that are non-solid.  Returns the number of
+// non-solid cells.
+int64_t classify_blocks(const lbm_params& p, const uint8_t* solid, std::vector<uint8_t>& bfluid,
+                        std::vector<uint8_t>& binlet, std::vector<float>& bfrac) {
+  const int nbx = padded(p.nx) / kB, nby = padded(p.ny) / kB, nbz = padded(p.nz) / kB;
+  const int nb = nbx * nby * nbz;
+  bfluid.assign(nb, 0);
+  binlet.assign(nb, 0);
+  bfrac.assign(nb, 0.0f);
+  int64_t cells = 0;
+  for (int z = 0; z < p.nz; ++z)
+    for (int y = 0; y < p.ny; ++y)
+      for (int x = 0; x < p.nx; ++x) {
+        const int64_t n = x + (int64_t)p.nx * (y + (int64_t)p.ny * z);
+        if (solid && solid[n]) continue;
+        const int b = x / kB + nbx * (y / kB + nby * (z / kB));
+        bfluid[b] = 1;
+        bfrac[b] += 1.0f / (float)kCells;
+        cells++;
+        const bool on[6] = {x == 0, x == p.nx - 1, y == 0, y == p.ny - 1, z == 0, z == p.nz - 1};
+        for (int f = 0; f < 6; ++f)
+          if (on[f] && p.bc[f] == LBM_BC_INLET) binlet[b] = 1;
+      }
+  return cells;
+}
+
+int pool_capacity(const lbm_params& p, int n_fluid_blocks, int nb) {
+  int cap = p.pool_blocks > 0 ? p.pool_blocks : n_fluid_blocks;
+  if (cap > nb) cap = nb;
+  if (cap < 1) cap = 1;
+  return cap;
+}
+
+// Bytes lbm_create reserves before any geometry.
+constexpr int64_t kCreateBytes = sizeof(float) * 128 + sizeof(int) * 4 + sizeof(double) * 4 +
+                                 sizeof(int32_t) * kNumCtrl + sizeof(unsigned long long) * 4;
+
 int validate(const lbm_params* p) {
   if (!p) return fail(nullptr, LBM_EINVAL, "params is NULL");
   if (p->block != kB) return fail(nullptr, LBM_EINVAL, "block must be 16 (got %d)", p->block);
-  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->nx % kB || p->ny % kB || p->nz % kB)
-    return fail(nullptr, LBM_EINVAL, "nx, ny, nz must be positive multiples of 16 (got %d %d %d)", p->nx, p->ny,
-                p->nz);
-  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31)
-    return fail(nullptr, LBM_EINVAL, "lattice larger than 2^31 cells");
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0)
+    return fail(nullptr, LBM_EINVAL, "nx, ny, nz must be positive (got %d %d %d)", p->nx, p->ny, p->nz);
+  {
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int d = 0; d < 3; ++d)
+      if (p->bc[2 * d] == LBM_BC_PERIODIC && n[d] % kB)
+        return fail(nullptr, LBM_EINVAL,
+                    "a periodic axis must be a multiple of 16 (axis %d has %d cells); only non-periodic axes "
+                    "are padded with solid cells", d, n[d]);
+  }
+  if ((int64_t)padded(p->nx) * padded(p->ny) * padded(p->nz) > (int64_t)1 << 31)
+    return fail(nullptr, LBM_EINVAL, "lattice larger than 2^31 cells (after padding to whole blocks)");
   if (p->ncomp != 1 && p->ncomp != 2) return fail(nullptr, LBM_EINVAL, "ncomp must be 1 or 2 (got %d)", p->ncomp);
   if (p->shell_width < 1 || p->shell_width > kB / 2)
     return fail(nullptr, LBM_EINVAL, "shell_width must be in 1..8 (got %d)", p->shell_width);
@@ -179,6 +276,12 @@ int validate(const lbm_params* p) {
     return fail(nullptr, LBM_EINVAL, "store must be LBM_STORE_F32 or LBM_STORE_F16DEV (got %d)", p->store);
   if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
+  if (p->store == LBM_STORE_F32 || p->store == LBM_STORE_F16DEV) {
+    const int lim = max_slots(p->store);
+    if (p->pool_blocks > lim)
+      return fail(nullptr, LBM_EINVAL, "pool_blocks %d exceeds the %d block slots the kernels can address with this "
+                  "store", p->pool_blocks, lim);
+  }
   if (p->pattern != LBM_PATTERN_AB && p->pattern != LBM_PATTERN_AA)
     return fail(nullptr, LBM_EINVAL, "pattern must be LBM_PATTERN_AB or LBM_PATTERN_AA");
   for (int a = 0; a < p->ncomp; ++a) {
@@ -289,9 +392,9 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   P.nx = p->nx;
   P.ny = p->ny;
   P.nz = p->nz;
-  P.nbx = p->nx / kB;
-  P.nby = p->ny / kB;
-  P.nbz = p->nz / kB;
+  P.nbx = padded(p->nx) / kB;
+  P.nby = padded(p->ny) / kB;
+  P.nbz = padded(p->nz) / kB;
   P.nb = P.nbx * P.nby * P.nbz;
   P.ncomp = p->ncomp;
   P.shell = p->shell_width;
@@ -369,6 +472,27 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   return LBM_OK;
 }
 
+int lbm_plan_bytes(const lbm_params* p, const uint8_t* solid, int64_t* bytes) {
+  g_create_error.clear();
+  if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+  *bytes = 0;
+  const int rc = validate(p);
+  if (rc) return rc;
+  std::vector<uint8_t> bfluid, binlet;
+  std::vector<float> bfrac;
+  classify_blocks(*p, solid, bfluid, binlet, bfrac);
+  int n_fluid = 0;
+  for (uint8_t v : bfluid) n_fluid += v;
+  const int nb = (int)bfluid.size();
+  const int cap = pool_capacity(*p, n_fluid, nb);
+  if (cap > max_slots(p->store))
+    return fail(nullptr, LBM_EINVAL, "%d block slots needed, but the kernels address at most %d with this store", cap,
+                max_slots(p->store));
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  *bytes = kCreateBytes + geometry_layout(*p, cap, nb, N).total(*p);
+  return LBM_OK;
+}
+
 int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const double* u0) {
   if (!h) return LBM_EINVAL;
   if (h->geometry) return fail(h, LBM_ESTATE, "lbm_set_geometry called twice");
@@ -376,59 +500,44 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   Buffers& D = h->D;
   const int64_t N = (int64_t)P.nx * P.ny * P.nz;
   // block classification on the host
-  h->bfluid_h.assign(P.nb, 0);
-  h->binlet_h.assign(P.nb, 0);
-  h->bfrac_h.assign(P.nb, 0.0f);
-  h->fluid_cells = 0;
-  for (int z = 0; z < P.nz; ++z)
-    for (int y = 0; y < P.ny; ++y)
-      for (int x = 0; x < P.nx; ++x) {
-        const int64_t n = x + (int64_t)P.nx * (y + (int64_t)P.ny * z);
-        if (solid && solid[n]) continue;
-        const int b = x / kB + P.nbx * (y / kB + P.nby * (z / kB));
-        h->bfluid_h[b] = 1;
-        h->bfrac_h[b] += 1.0f / (float)kCells;
-        h->fluid_cells++;
-        const bool on[6] = {x == 0, x == P.nx - 1, y == 0, y == P.ny - 1, z == 0, z == P.nz - 1};
-        for (int f = 0; f < 6; ++f)
-          if (on[f] && P.bc[f] == kInletFace) h->binlet_h[b] = 1;
-      }
+  h->fluid_cells = classify_blocks(h->user, solid, h->bfluid_h, h->binlet_h, h->bfrac_h);
   h->n_fluid_blocks = 0;
   for (int b = 0; b < P.nb; ++b) h->n_fluid_blocks += h->bfluid_h[b];
-  int cap = h->user.pool_blocks > 0 ? h->user.pool_blocks : h->n_fluid_blocks;
-  if (cap > P.nb) cap = P.nb;
-  if (cap < 1) cap = 1;
+  const int cap = pool_capacity(h->user, h->n_fluid_blocks, P.nb);
+  if (cap > max_slots(h->user.store))
+    return fail(h, LBM_EINVAL,
+                "%d block slots needed, but the kernels address at most %d with this store (32-bit offsets "
+                "within a pair of population planes); use the FP16-deviation store or a smaller lattice",
+                cap, max_slots(h->user.store));
   P.capacity = cap;
-  const int64_t plane = (int64_t)(cap + 1) * kCells;
-  P.plane = (uint32_t)plane;
-  const size_t fsz = h->user.store == LBM_STORE_F16DEV ? 2 : 4;
+  P.plane = (uint32_t)((int64_t)(cap + 1) * kCells);
+  const GeometryLayout L = geometry_layout(h->user, cap, P.nb, N);
   const bool f16 = h->user.store == LBM_STORE_F16DEV;
   const bool aa = in_place(h);
-  D.f[0] = dev_alloc(h, fsz * P.ncomp * kQ * plane);
-  D.f[1] = aa ? D.f[0] : dev_alloc(h, fsz * P.ncomp * kQ * plane);
-  D.psi = aa ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
-  D.rho[0] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
-  D.rho[1] = f16 ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * plane) : nullptr;
-  D.mask = (uint32_t*)dev_alloc(h, sizeof(uint32_t) * plane);
-  D.uprev = h->user.progressive ? (float*)dev_alloc(h, sizeof(float) * P.ncomp * 3 * plane) : nullptr;
-  D.block_slot = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
-  D.slot_block = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
-  D.order = (int32_t*)dev_alloc(h, sizeof(int32_t) * cap);
-  D.bfluid = (uint8_t*)dev_alloc(h, P.nb);
-  D.solid = (uint8_t*)dev_alloc(h, (size_t)N);
-  D.request = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
-  D.expose = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
-  D.act_step = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
-  D.bfrac = (float*)dev_alloc(h, sizeof(float) * P.nb);
-  D.cand = (int32_t*)dev_alloc(h, sizeof(int32_t) * P.nb);
-  D.trace = (int32_t*)dev_alloc(h, sizeof(int32_t) * 2 * P.trace_cap);
+  D.f[0] = dev_alloc(h, L.f);
+  D.f[1] = aa ? D.f[0] : dev_alloc(h, L.f);
+  D.psi = aa ? (float*)dev_alloc(h, L.psi) : nullptr;
+  D.rho[0] = f16 ? (float*)dev_alloc(h, L.rho) : nullptr;
+  D.rho[1] = f16 ? (float*)dev_alloc(h, L.rho) : nullptr;
+  D.mask = (uint32_t*)dev_alloc(h, L.mask);
+  D.uprev = h->user.progressive ? (float*)dev_alloc(h, L.uprev) : nullptr;
+  D.block_slot = (int32_t*)dev_alloc(h, L.per_block_i32);
+  D.slot_block = (int32_t*)dev_alloc(h, L.per_slot_i32);
+  D.order = (int32_t*)dev_alloc(h, L.per_slot_i32);
+  D.bfluid = (uint8_t*)dev_alloc(h, L.per_block_u8);
+  D.solid = (uint8_t*)dev_alloc(h, L.solid);
+  D.request = (int32_t*)dev_alloc(h, L.per_block_i32);
+  D.expose = (int32_t*)dev_alloc(h, L.per_block_i32);
+  D.act_step = (int32_t*)dev_alloc(h, L.per_block_i32);
+  D.bfrac = (float*)dev_alloc(h, L.per_block_i32);
+  D.cand = (int32_t*)dev_alloc(h, L.per_block_i32);
+  D.trace = (int32_t*)dev_alloc(h, L.trace);
   if (!D.f[0] || !D.f[1] || (aa && !D.psi) || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
       !D.slot_block || !D.order || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
       !D.cand || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
-  h->slot_bytes = (int64_t)kCells * ((int64_t)(aa ? 1 : 2) * fsz * P.ncomp * kQ + (f16 ? 8 * P.ncomp : 0) +
-                                     (aa ? 4 * P.ncomp : 0) + 4 + (h->user.progressive ? 12 * P.ncomp : 0));
+  h->slot_bytes = L.slot_bytes;
   // initial fields, FP32; NaN marks a component of a cell at the rest state
   if (rho0 || u0) {
     std::vector<float> r((size_t)P.ncomp * N), u(u0 ? (size_t)3 * N : 0);
@@ -441,12 +550,12 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
       }
     if (u0)
       for (int64_t k = 0; k < 3 * N; ++k) u[k] = (float)u0[k];
-    h->init_rho = (float*)dev_alloc(h, sizeof(float) * r.size());
+    h->init_rho = (float*)dev_alloc(h, L.init_rho);
     if (!h->init_rho) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
     HIP_TRY(h, hipMemcpy(h->init_rho, r.data(), sizeof(float) * r.size(), hipMemcpyHostToDevice));
     D.init_rho = h->init_rho;
     if (u0) {
-      h->init_u = (float*)dev_alloc(h, sizeof(float) * u.size());
+      h->init_u = (float*)dev_alloc(h, L.init_u);
       if (!h->init_u) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
       HIP_TRY(h, hipMemcpy(h->init_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice));
       D.init_u = h->init_u;
@@ -835,6 +944,10 @@ int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
     if (h->step != h0->step || h->rbuf != h0->rbuf)
       return fail(nullptr, LBM_EINVAL, "batch: member %d is at another step", i);
     if (h->prop_enabled) return fail(nullptr, LBM_EINVAL, "batch: member %d has the proposal enabled", i);
+    // one member twice would have two workgroups update its blocks and
+    // tables unsynchronised, and would advance its step count twice
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == h) return fail(nullptr, LBM_EINVAL, "batch: members %d and %d are the same handle", j, i);
   }
   lbm_batch* b = new lbm_batch();
   b->members.assign(hs, hs + n);

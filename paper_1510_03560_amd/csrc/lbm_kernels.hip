@@ -664,8 +664,12 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
       const uint32_t cid = (uint32_t)slot * kCells + c;
       uint32_t m = 0u;
       long long n = -1;
-      if (!rest_slot) {
-        const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
+      const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
+      // cells beyond the lattice (padding of a block that a non-periodic
+      // face cuts) are solid
+      const bool pad = !rest_slot && (X >= P.nx || Y >= P.ny || Z >= P.nz);
+      if (pad) m = (uint32_t)kSolid << kKindShift;
+      if (!rest_slot && !pad) {
         n = X + (long long)P.nx * (Y + (long long)P.ny * Z);
         uint32_t kind = D.solid[n] ? kSolid : kFluid;
         if (kind == kFluid) {
@@ -701,7 +705,6 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
       uint32_t stash[kQ];
       for (int i = 0; i < kQ; ++i) stash[i] = ~0u;
       if (mode == kInitStash && !rest_slot && ((m >> kKindShift) & 3u) != kSolid) {
-        const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
         for (int i = 1; i < kQ; ++i) {
           if ((m >> i) & 1u) continue;  // bounced: rest, like every link from a solid cell
           const int sx = (X - dir_ex(i) + P.nx) % P.nx, sy = (Y - dir_ey(i) + P.ny) % P.ny,
@@ -1932,7 +1935,9 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
     const uint32_t cid = own_base + cell_of(x, y, z);
     const uint32_t m = D.mask[cid];
     const bool sol = ((m >> kKindShift) & 3u) == kSolid;
-    const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
+    const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
+    if (X >= P.nx || Y >= P.ny || Z >= P.nz) continue;  // padding: not part of the lattice
+    const long long n = X + (long long)P.nx * (Y + (long long)P.ny * (long long)Z);
     float mr = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);

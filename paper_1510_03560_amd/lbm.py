@@ -59,8 +59,8 @@ class lbm_stats_t(C.Structure):
 
 
 _lib = None
-EXPORTS = ["lbm_create", "lbm_set_geometry", "lbm_activate", "lbm_step", "lbm_sync", "lbm_moments",
-           "lbm_moments_device", "lbm_stats", "lbm_trace", "lbm_debug_fields", "lbm_timing_enable",
+EXPORTS = ["lbm_create", "lbm_set_geometry", "lbm_plan_bytes", "lbm_activate", "lbm_step", "lbm_sync",
+           "lbm_moments", "lbm_moments_device", "lbm_stats", "lbm_trace", "lbm_debug_fields", "lbm_timing_enable",
            "lbm_timing_read", "lbm_kernel_name", "lbm_destroy", "lbm_last_error"]
 
 
@@ -81,6 +81,7 @@ def load():
     vp, i32, d, u8 = C.c_void_p, C.c_int32, C.c_double, C.c_uint8
     lib.lbm_create.argtypes = [P(lbm_params), vp, P(lbm_allocator), P(vp)]
     lib.lbm_set_geometry.argtypes = [vp, P(u8), P(d), P(d)]
+    lib.lbm_plan_bytes.argtypes = [P(lbm_params), P(u8), P(C.c_int64)]
     lib.lbm_activate.argtypes = [vp, P(i32), i32]
     lib.lbm_step.argtypes = [vp, i32]
     lib.lbm_sync.argtypes = [vp]
@@ -155,6 +156,13 @@ def lbm_set_geometry(h, solid=None, rho0=None, u0=None):
     r = None if rho0 is None else np.ascontiguousarray(rho0, dtype=np.float64)
     u = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64)
     _check(load().lbm_set_geometry(h, _ptr(s, C.c_uint8), _ptr(r, C.c_double), _ptr(u, C.c_double)), h)
+
+
+def lbm_plan_bytes(params: lbm_params, solid=None) -> int:
+    s = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+    out = C.c_int64()
+    _check(load().lbm_plan_bytes(C.byref(params), _ptr(s, C.c_uint8), C.byref(out)), None)
+    return int(out.value)
 
 
 def lbm_activate(h, block_ids):
@@ -232,17 +240,46 @@ def torch_stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def torch_allocator(stream=None) -> lbm_allocator:
+    """An lbm_allocator over PyTorch's caching allocator on the current
+    device (requires a GPU): alloc is torch.cuda.caching_allocator_alloc on
+    `stream` (default: torch's current stream), free is
+    caching_allocator_delete.  A request torch cannot serve returns NULL, which
+    the library reports as LBM_ENOMEM.  stream: a raw HIP stream handle.  Keep the returned object alive as long
+    as any handle created with it (it owns the two C callbacks)."""
+    import torch
+    dev = torch.cuda.current_device()
+    st = int(torch.cuda.current_stream(dev).cuda_stream if stream is None else stream)
+    alloc_t = dict(lbm_allocator._fields_)["alloc"]
+    free_t = dict(lbm_allocator._fields_)["free"]
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, st))
+        except (RuntimeError, MemoryError):  # torch.OutOfMemoryError is a RuntimeError
+            return None
+
+    def _free(ptr, _ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    return lbm_allocator(alloc_t(_alloc), free_t(_free), None)
+
+
 class Simulation:
     """A handle plus the geometry it was given.
 
     case: a workloads.Case (params dict, solid, rho0, u0, active_blocks).
     store: STORE_F32 or STORE_F16DEV.  progressive: defaults to
     case.active_blocks is not None.  pattern: PATTERN_AB (two population
-    buffers) or PATTERN_AA (one buffer updated in place).
+    buffers) or PATTERN_AA (one buffer updated in place).  allocator:
+    "torch" (default) takes every device buffer from PyTorch's caching
+    allocator on the handle's stream; None lets the library call hipMalloc;
+    an lbm_allocator is used as given.
     """
 
     def __init__(self, case, store: int = STORE_F32, progressive: bool | None = None, pool_blocks: int = 0,
-                 stream=None, pattern: int = PATTERN_AB):
+                 stream=None, pattern: int = PATTERN_AB, allocator="torch"):
         if progressive is None:
             progressive = case.active_blocks is not None
         self.case = case
@@ -250,7 +287,13 @@ class Simulation:
                                   pattern=pattern)
         self.ncomp = self.params.ncomp
         self.N = self.params.nx * self.params.ny * self.params.nz
-        self.h = lbm_create(self.params, stream=stream if stream is not None else torch_stream())
+        stream = stream if stream is not None else torch_stream()
+        if isinstance(allocator, str):
+            if allocator != "torch":
+                raise ValueError(f"unknown allocator {allocator!r}")
+            allocator = torch_allocator(stream)
+        self._allocator = allocator  # keeps the callbacks alive with the handle
+        self.h = lbm_create(self.params, stream=stream, allocator=allocator)
         try:
             lbm_set_geometry(self.h, case.solid, case.rho0, case.u0)
             if progressive and case.active_blocks is not None:

@@ -60,7 +60,7 @@ class Case:
     def n_blocks(self) -> int:
         p = self.params
         B = p["block"]
-        return (p["nx"] // B) * (p["ny"] // B) * (p["nz"] // B)
+        return (-(-p["nx"] // B)) * (-(-p["ny"] // B)) * (-(-p["nz"] // B))
 
     def static_twin(self) -> "Case":
         """The same run on the static (fully meshed) grid."""
@@ -213,7 +213,8 @@ def porous_injection(n: int = 192, seed: int = 0, porosity: float = 0.65, steps:
     """Liquid injected through a porous medium (progressive mesh).
 
     Geometry: random non-overlapping spheres of radius 4-12 (random_spheres).
-    Face x = 0 is an equilibrium inlet (component 1 at 6.5, component 2 at
+    shape: (nx, ny, nz) instead of n^3; sides need not be multiples of the
+    block (every face is non-periodic).  Face x = 0 is an equilibrium inlet (component 1 at 6.5, component 2 at
     0.1, velocity (0.02, 0, 0)); face x = nx-1 is an equilibrium outlet at the
     background state; the y and z faces are walls.  The pores start at rest
     with component 1 at 0.38 and component 2 at 0.38.  Only the blocks of the
@@ -224,7 +225,9 @@ def porous_injection(n: int = 192, seed: int = 0, porosity: float = 0.65, steps:
     params = dict(FLUID, nx=nx, ny=ny, nz=nz, block=block, ncomp=2, shell_width=2, S=0.0,
                   bc=(INLET, OUTLET, WALL, WALL, WALL, WALL), body=((0.0,) * 3,) * 2,
                   inlet_rho=(6.5, 0.1), inlet_u=(0.02, 0.0, 0.0), bg_rho=(0.38, 0.38))
-    nbx, nby, nbz = nx // block, ny // block, nz // block
+    # blocks of the lattice padded to whole blocks (the library pads a
+    # non-periodic axis whose length is not a multiple of the block with solid)
+    nbx, nby, nbz = -(-nx // block), -(-ny // block), -(-nz // block)
     act = None
     if progressive:
         act = np.zeros((nbz, nby, nbx), dtype=np.uint8)

@@ -86,7 +86,8 @@ def test_struct_layout_matches_header(L, tmp_path):
 
 
 @pytest.mark.parametrize("field,value,needle", [
-    ("nx", 20, "multiples of 16"),
+    ("nx", 20, "periodic axis"),
+    ("nx", 0, "positive"),
     ("block", 8, "block must be 16"),
     ("ncomp", 3, "ncomp"),
     ("shell_width", 0, "shell_width"),
@@ -130,3 +131,66 @@ def test_null_handle_calls(L):
     lib = L.load()
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_destroy(None) == 0
+
+
+def test_pool_beyond_32bit_offsets_rejected(L):
+    """The kernels address a pair of population planes with 32-bit byte
+    offsets: a pool of more than 131071 slots (FP32 store) or 262143 (FP16
+    store) is refused before anything is allocated."""
+    for store, lim in ((L.STORE_F32, 131071), (L.STORE_F16DEV, 262143)):
+        p = L.make_params(W.droplet_periodic(32, 0).params, store=store, pool_blocks=lim + 1)
+        with pytest.raises(L.LbmError) as ei:
+            L.lbm_create(p, stream=0)
+        assert ei.value.code == -1 and "pool_blocks" in str(ei.value)
+        p.pool_blocks = lim
+        assert L.lbm_plan_bytes(p) > 0  # at the limit: accepted (pool clamped to the 8 blocks)
+    # a lattice whose fluid blocks alone exceed the FP32 limit: 1024 x 1024 x 512
+    # cells, no solid, 131072 blocks (planned on the host only, never allocated)
+    q = dict(W.porous_injection(64, 0).params, nx=1024, ny=1024, nz=512)
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F32))
+    assert "131071" in str(ei.value)
+    assert L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F16DEV)) > 0
+
+
+def test_refusing_allocator_gives_enomem(L):
+    """lbm_create takes every device buffer from the caller's allocator; one
+    that refuses makes it return LBM_ENOMEM (before any device call)."""
+    calls = []
+    alloc_t = dict(L.lbm_allocator._fields_)["alloc"]
+    free_t = dict(L.lbm_allocator._fields_)["free"]
+    a = L.lbm_allocator(alloc_t(lambda n, ctx: calls.append(n)), free_t(lambda p, ctx: None), None)
+    p = L.make_params(W.droplet_periodic(32, 0).params)
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_create(p, stream=0, allocator=a)
+    assert ei.value.code == -3
+    assert "allocation failed" in str(ei.value)
+    assert len(calls) >= 1
+
+
+def test_padded_lattice_plan(L):
+    """Non-periodic axes of any length are padded to whole 16^3 blocks; a
+    periodic axis must be a multiple of 16."""
+    c = W.porous_injection(0, seed=3, shape=(40, 24, 56))
+    p = L.make_params(c.params)
+    padded = L.lbm_plan_bytes(p, c.solid)
+    assert padded > 0
+    # 3 x 2 x 4 blocks of the padded 48 x 32 x 64 lattice, all holding fluid
+    q = L.make_params(W.porous_injection(0, seed=3, shape=(48, 32, 64)).params)
+    assert L.lbm_plan_bytes(q) - padded == (48 * 32 * 64 - 40 * 24 * 56)  # only the solid-flag array differs
+    d = L.make_params(W.droplet_periodic(32, 0).params)
+    d.nx = 40
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_create(d, stream=0)
+    assert "periodic axis" in str(ei.value)
+
+
+def test_batch_rejects_the_same_simulation_twice():
+    from paper_1510_03560_amd import batch
+
+    class Fake:
+        h = None
+
+    s = Fake()
+    with pytest.raises(ValueError):
+        batch.Batch([s, s])
