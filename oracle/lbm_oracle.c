@@ -304,12 +304,21 @@ void orc_destroy(orc_sim* s) {
 orc_sim* orc_create(const orc_params* p, const uint8_t* solid, const double* rho0, const double* u0,
                     const uint8_t* active_blocks) {
   if (p->ncomp < 1 || p->ncomp > 2 || p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->block <= 0) return NULL;
-  if (p->nx % p->block || p->ny % p->block || p->nz % p->block) return NULL;
+  /* a periodic axis wraps whole blocks; along the other axes the last block
+   * may extend past the lattice (uneven edges: the cells it would hold
+   * beyond the lattice do not exist, exactly as solid padding behaves) */
+  {
+    int n[3] = {p->nx, p->ny, p->nz};
+    for (int d = 0; d < 3; d++)
+      if (p->bc[2 * d] == ORC_PERIODIC && n[d] % p->block) return NULL;
+  }
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   s->p = *p;
   s->e = eos_setup(p);
   s->N = (int64_t)p->nx * p->ny * p->nz;
-  s->nbx = p->nx / p->block; s->nby = p->ny / p->block; s->nbz = p->nz / p->block;
+  s->nbx = (p->nx + p->block - 1) / p->block;
+  s->nby = (p->ny + p->block - 1) / p->block;
+  s->nbz = (p->nz + p->block - 1) / p->block;
   s->nb = s->nbx * s->nby * s->nbz;
   int64_t N = s->N;
   int nc = p->ncomp;
@@ -543,6 +552,7 @@ static void one_step(orc_sim* s) {
               for (int lz = lo[2]; lz <= hi[2] && !fire; lz++)
                 for (int ly = lo[1]; ly <= hi[1] && !fire; ly++)
                   for (int lx = lo[0]; lx <= hi[0] && !fire; lx++) {
+                    if (bx * B + lx >= p->nx || by * B + ly >= p->ny || bz * B + lz >= p->nz) continue;
                     int64_t n = cell_index(s, bx * B + lx, by * B + ly, bz * B + lz);
                     if (s->kind[n] == K_SOLID) continue;
                     for (int a = 0; a < nc && !fire; a++) {
