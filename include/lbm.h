@@ -199,6 +199,23 @@ int lbm_sync(lbm_t* h);
  * Synchronous.  Errors: LBM_ESTATE, LBM_ENUMERIC, LBM_ENOMEM, LBM_EHIP. */
 int lbm_moments(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same fields, values and errors as
+ * lbm_moments, staged through a fixed device array that the library holds on
+ * each GPU it runs on until the process ends (64 MiB, 16777216 floats), so
+ * the call allocates and frees nothing.  The requested fields must fit it:
+ * ncomp*N floats for rho, ncomp*3*N for u, 3*N for umix and N/4 for active,
+ * each rounded up to 64 (every field of two components: about 1.49 million
+ * cells, e.g. 112^3; densities alone: 8.38 million); a larger request returns LBM_EINVAL with the sizes in the message.
+ * The array is shared by every handle on the GPU and keeps the last call's
+ * contents (each call writes all it reads back): calls that overlap on one
+ * GPU, from several threads or streams, race and must be serialised by the
+ * caller.  Unlike lbm_moments it does not release the initial fields after
+ * the first step (that happens at the next lbm_moments, lbm_sync or
+ * lbm_destroy).  Synchronous.  Errors: LBM_EINVAL, LBM_ESTATE, LBM_ENUMERIC,
+ * LBM_ENOMEM (pool full flag), LBM_EHIP. */
+int lbm_moments_noalloc(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active);
+
 /* Same fields as lbm_moments, written as FP32 into caller-owned DEVICE
  * buffers (rho: ncomp*N, u: ncomp*3*N, umix: 3*N; any may be NULL), enqueued
  * on the handle's stream without waiting. */

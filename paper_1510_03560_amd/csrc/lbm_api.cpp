@@ -62,6 +62,7 @@ struct lbm_handle {
   bool nact_pending = false;
   int ids_cap = 0;
   double* mass_dev = nullptr;
+  float* staging = nullptr;    // this device's copy of the static staging array (lbm_moments_noalloc)
   float* scratch_f = nullptr;  // small device scratch (rest state)
   int* scratch_i = nullptr;
   bool timing = false;
@@ -456,6 +457,15 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
     delete h;
     return fail(nullptr, LBM_EINVAL, "the rest state did not converge (body force?)");
   }
+  // the static staging array of lbm_moments_noalloc on this device (looked
+  // up once per device with that device current)
+  e = static_staging(&h->staging);
+  if (e != hipSuccess) {
+    std::string msg = hipGetErrorString(e);
+    dev_free_all(h);
+    delete h;
+    return fail(nullptr, LBM_EHIP, "static staging lookup: %s", msg.c_str());
+  }
   for (int a = 0; a < kMaxComp; ++a) {
     const int aa = a < p->ncomp ? a : 0;
     for (int i = 0; i < kQ; ++i) {
@@ -770,6 +780,63 @@ int lbm_moments(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active)
               bslot[x / kB + P.nbx * (y / kB + P.nby * (z / kB))] >= 0 ? 1 : 0;
   }
   return check_device_flags(h);
+}
+
+namespace {
+// Widens n FP32 values to FP64 in place: the floats occupy the upper half
+// of out's 8n bytes.  Ascending order reads each float before the double
+// written at the same index (or a lower one) can overwrite it.
+void widen_in_place(double* out, size_t n) {
+  const char* src = reinterpret_cast<const char*>(out) + 4 * n;
+  for (size_t k = 0; k < n; ++k) {
+    float v;
+    std::memcpy(&v, src + 4 * k, sizeof v);
+    out[k] = (double)v;
+  }
+}
+}  // namespace
+
+int lbm_moments_noalloc(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active) {
+  if (!h) return LBM_EINVAL;
+  if (!h->geometry) return fail(h, LBM_ESTATE, "lbm_moments_noalloc before lbm_set_geometry");
+  const Params& P = h->P;
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t nr = rho ? (size_t)P.ncomp * N : 0, nu = u ? (size_t)P.ncomp * 3 * N : 0, nm = umix ? 3 * N : 0;
+  const size_t na = active ? (N + 3) / 4 : 0;  // N bytes
+  auto up = [](size_t n) { return (n + 63) & ~(size_t)63; };  // 256-byte aligned segments
+  const size_t need = up(nr) + up(nu) + up(nm) + up(na);
+  if (need > kStaticStagingFloats)
+    return fail(h, LBM_EINVAL,
+                "lbm_moments_noalloc: the requested fields need %zu floats of staging, the static array holds %zu "
+                "(about %zu cells with every field of two components)",
+                need, (size_t)kStaticStagingFloats, (size_t)kStaticStagingFloats * 4 / 45);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  int rc = check_device_flags(h);
+  if (rc) return rc;
+  float* next = h->staging;
+  float* d_r = rho ? next : nullptr;
+  next += up(nr);
+  float* d_u = u ? next : nullptr;
+  next += up(nu);
+  float* d_m = umix ? next : nullptr;
+  next += up(nm);
+  uint8_t* d_a = active ? reinterpret_cast<uint8_t*>(next) : nullptr;
+  // every element copied out is written first (the default fill covers the
+  // whole lattice), so the array's previous contents never show
+  hipError_t e = hipSuccess;
+  if (rho || u || umix) e = launch_export(P, h->D, h->rbuf, read_mode(h), d_r, d_u, d_m, h->stream);
+  if (e == hipSuccess && active) e = launch_active_cells(P, h->D, d_a, h->stream);
+  if (e != hipSuccess) return fail(h, LBM_EHIP, "export: %s", hipGetErrorString(e));
+  // FP32 fields land in the upper half of the caller's FP64 arrays
+  if (rho) HIP_TRY(h, hipMemcpyAsync((char*)rho + 4 * nr, d_r, 4 * nr, hipMemcpyDeviceToHost, h->stream));
+  if (u) HIP_TRY(h, hipMemcpyAsync((char*)u + 4 * nu, d_u, 4 * nu, hipMemcpyDeviceToHost, h->stream));
+  if (umix) HIP_TRY(h, hipMemcpyAsync((char*)umix + 4 * nm, d_m, 4 * nm, hipMemcpyDeviceToHost, h->stream));
+  if (active) HIP_TRY(h, hipMemcpyAsync(active, d_a, N, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (rho) widen_in_place(rho, nr);
+  if (u) widen_in_place(u, nu);
+  if (umix) widen_in_place(umix, nm);
+  return LBM_OK;
 }
 
 int lbm_stats(lbm_t* h, lbm_stats_t* out) {

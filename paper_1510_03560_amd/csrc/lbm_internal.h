@@ -166,6 +166,13 @@ hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool fi
                              bool in_place, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
+// out[n] = 1 for cells of active blocks (lattice-wide, N bytes).
+hipError_t launch_active_cells(const Params& P, const Buffers& D, uint8_t* out, hipStream_t stream);
+// Staging for lbm_moments_noalloc: a fixed device array of
+// kStaticStagingFloats floats, one per GPU.  Returns its address on the
+// current device (looked up once per device, thread-safe).
+constexpr size_t kStaticStagingFloats = size_t(16) << 20;  // 64 MiB
+hipError_t static_staging(float** out);
 hipError_t launch_mass(const Params& P, const Buffers& D, int rbuf, int rd, double* out2,
                        hipStream_t stream);
 // Test dump: psi_slots = device scratch of ncomp planes; psi (ncomp*N) and

@@ -40,6 +40,7 @@
 
 #include <hip/hip_fp16.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lbm_internal.h"
@@ -1909,6 +1910,15 @@ __global__ void k_fill_default(Params P, Buffers D, float* rho, float* u, float*
   }
 }
 
+// Per lattice cell: 1 if its block is active.
+__global__ void k_active_cells(Params P, Buffers D, uint8_t* out) {
+  const long long N = (long long)P.nx * P.ny * P.nz;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(n % P.nx), y = (int)((n / P.nx) % P.ny), z = (int)(n / ((long long)P.nx * P.ny));
+    out[n] = D.block_slot[x / kB + P.nbx * (y / kB + P.nby * (z / kB))] >= 0 ? 1 : 0;
+  }
+}
+
 // Moments (Eq 4-5) of the active blocks into lattice-wide arrays.
 template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rbuf, float* rho, float* u,
@@ -2221,6 +2231,38 @@ struct MassL {
 };
 
 }  // namespace
+
+// ------------------------------------------------------ static staging
+// Device staging of the allocation-free moments export: one copy of this
+// array per GPU, held until the process ends.  Host code never uses the
+// name itself (on the host it is not a device address): static_staging()
+// looks up each device's copy with hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[kStaticStagingFloats];
+
+hipError_t static_staging(float** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    float* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_active_cells(const Params& P, const Buffers& D, uint8_t* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_active_cells, dim3(2048), dim3(256), 0, stream, P, D, out);
+  return hipGetLastError();
+}
 
 // --------------------------------------------------------------- launchers
 hipError_t launch_rest_state(const Params& P, const float* bg, float* out, int* iters, hipStream_t stream) {

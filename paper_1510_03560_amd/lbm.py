@@ -60,7 +60,7 @@ class lbm_stats_t(C.Structure):
 
 _lib = None
 EXPORTS = ["lbm_create", "lbm_set_geometry", "lbm_plan_bytes", "lbm_activate", "lbm_step", "lbm_sync",
-           "lbm_moments", "lbm_moments_device", "lbm_stats", "lbm_trace", "lbm_debug_fields", "lbm_timing_enable",
+           "lbm_moments", "lbm_moments_noalloc", "lbm_moments_device", "lbm_stats", "lbm_trace", "lbm_debug_fields", "lbm_timing_enable",
            "lbm_timing_read", "lbm_kernel_name", "lbm_destroy", "lbm_last_error"]
 
 
@@ -86,6 +86,7 @@ def load():
     lib.lbm_step.argtypes = [vp, i32]
     lib.lbm_sync.argtypes = [vp]
     lib.lbm_moments.argtypes = [vp, P(d), P(d), P(d), P(u8)]
+    lib.lbm_moments_noalloc.argtypes = [vp, P(d), P(d), P(d), P(u8)]
     lib.lbm_moments_device.argtypes = [vp, vp, vp, vp]
     lib.lbm_stats.argtypes = [vp, P(lbm_stats_t)]
     lib.lbm_trace.argtypes = [vp, P(i32), i32]
@@ -181,6 +182,11 @@ def lbm_sync(h):
 def lbm_moments(h, rho=None, u=None, umix=None, active=None):
     _check(load().lbm_moments(h, _ptr(rho, C.c_double), _ptr(u, C.c_double), _ptr(umix, C.c_double),
                               _ptr(active, C.c_uint8)), h)
+
+
+def lbm_moments_noalloc(h, rho=None, u=None, umix=None, active=None):
+    _check(load().lbm_moments_noalloc(h, _ptr(rho, C.c_double), _ptr(u, C.c_double), _ptr(umix, C.c_double),
+                                      _ptr(active, C.c_uint8)), h)
 
 
 def lbm_moments_device(h, rho_ptr=0, u_ptr=0, umix_ptr=0):
