@@ -245,6 +245,20 @@ int lbm_debug_fields(lbm_t* h, int which, double* out);
  * inplace_psi, inplace_collide), the launch count and total milliseconds,
  * then resets. */
 int lbm_timing_enable(lbm_t* h, int enable);
+
+/* Work split of the step kernel (a performance setting; results are the
+ * same bits for every choice).  The fused kernel of LBM_PATTERN_AB sweeps
+ * each active block's planes with workgroups of one thread per column of
+ * the block: planes_per_workgroup = 16 gives each block one workgroup
+ * (16 cells per thread), 8 two (8 cells per thread, plus the two halo
+ * planes each), 4 four.  0 (the default) chooses per step: the smallest
+ * number of planes such that the active blocks, as last seen by the host,
+ * times the workgroups per block stay within target_workgroups (default
+ * 320, a little above one workgroup per compute unit: measured on MI355X,
+ * splitting pays only while fewer blocks than compute units are active).  More workgroups per block fill the GPU when few blocks are active,
+ * at the price of re-reading the halo planes.  lbm_batch.h batches use the
+ * setting of their first member.  Errors: LBM_EINVAL. */
+int lbm_set_split(lbm_t* h, int32_t planes_per_workgroup, int32_t target_workgroups);
 int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n);
 const char* lbm_kernel_name(int32_t k);
 #define LBM_NUM_KERNELS 7

@@ -65,6 +65,12 @@ struct lbm_handle {
   float* staging = nullptr;    // this device's copy of the static staging array (lbm_moments_noalloc)
   float* scratch_f = nullptr;  // small device scratch (rest state)
   int* scratch_i = nullptr;
+  // step kernel workgroups per block: split_planes > 0 fixes the planes each
+  // takes (16 / parts); 0 picks the most parts (1, 2, 4) that keep
+  // n_est * parts within split_target workgroups
+  int split_planes = 0;
+  int split_target = 320;
+  int n_est = 0;                   // active blocks, as last seen by the host (never above the truth)
   bool timing = false;
   std::vector<hipEvent_t> ev;   // pairs per launch
   std::vector<int> ev_kernel;
@@ -184,7 +190,7 @@ struct GeometryLayout {
   int64_t total(const lbm_params& u) const {
     const bool aa = u.pattern == LBM_PATTERN_AA, f16 = u.store == LBM_STORE_F16DEV;
     return (int64_t)((aa ? 1 : 2) * f + (aa ? psi : 0) + (f16 ? 2 * rho : 0) + mask + (u.progressive ? uprev : 0) +
-                     6 * per_block_i32 + per_block_u8 + 2 * per_slot_i32 + solid + trace);
+                     6 * per_block_i32 + per_block_u8 + 3 * per_slot_i32 + solid + trace);
   }
 };
 
@@ -299,6 +305,7 @@ int validate(const lbm_params* p) {
 int check_device_flags(lbm_t* h) {
   int32_t ctrl[kNumCtrl];
   HIP_TRY(h, hipMemcpy(ctrl, h->D.ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+  h->n_est = ctrl[kNActive];
   if (ctrl[kNumeric]) return fail(h, LBM_ENUMERIC, "a density became non-positive or non-finite");
   if (ctrl[kPoolFull])
     return fail(h, LBM_ENOMEM, "block pool full (%d slots); raise pool_blocks", h->P.capacity);
@@ -306,6 +313,15 @@ int check_device_flags(lbm_t* h) {
 }
 
 bool in_place(const lbm_t* h) { return h->user.pattern == LBM_PATTERN_AA; }
+
+// Workgroups per block of the fused step kernel for about n active blocks.
+int step_parts(int split_planes, int split_target, int n) {
+  if (split_planes > 0) return kB / split_planes;
+  if (n < 1) n = 1;
+  int parts = 1;
+  while (parts < 4 && (int64_t)n * parts * 2 <= split_target) parts *= 2;
+  return parts;
+}
 
 // Where the populations of the current state are read (ReadMode).
 int read_mode(const lbm_t* h) {
@@ -534,6 +550,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.block_slot = (int32_t*)dev_alloc(h, L.per_block_i32);
   D.slot_block = (int32_t*)dev_alloc(h, L.per_slot_i32);
   D.order = (int32_t*)dev_alloc(h, L.per_slot_i32);
+  D.frontier = (int32_t*)dev_alloc(h, L.per_slot_i32);
   D.bfluid = (uint8_t*)dev_alloc(h, L.per_block_u8);
   D.solid = (uint8_t*)dev_alloc(h, L.solid);
   D.request = (int32_t*)dev_alloc(h, L.per_block_i32);
@@ -544,7 +561,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   D.trace = (int32_t*)dev_alloc(h, L.trace);
   if (!D.f[0] || !D.f[1] || (aa && !D.psi) || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
-      !D.slot_block || !D.order || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
+      !D.slot_block || !D.order || !D.frontier || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
       !D.cand || !D.trace)
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
   h->slot_bytes = L.slot_bytes;
@@ -611,6 +628,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   }
   int32_t ctrl[kNumCtrl] = {0};
   ctrl[kNActive] = (int32_t)sblock.size();
+  h->n_est = (int)sblock.size();
   HIP_TRY(h, hipMemcpy(D.ctrl, ctrl, sizeof ctrl, hipMemcpyHostToDevice));
   if (!sblock.empty()) {
     hipError_t e = launch_init_slots(P, D, 0, 0, (int)sblock.size(), false, true, h->stream);
@@ -675,6 +693,7 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
     int rc;
     if (h->user.progressive && h->nact_pending && hipEventQuery(h->nact_ev) == hipSuccess) {
       h->nact_pending = false;
+      if (*h->nact_pinned > h->n_est) h->n_est = *h->nact_pinned;
       if (*h->nact_pinned >= h->n_fluid_blocks) h->mesh_complete = true;
     }
     if (h->user.progressive && !h->mesh_complete) {
@@ -708,7 +727,8 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       rc = timed(h, 6, [&] { return launch_inplace_collide(P, h->D, rb, rd, h->stream); });
       if (rc) return rc;
     } else {
-      rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, h->stream); });
+      const int parts = step_parts(h->split_planes, h->split_target, h->n_est);
+      rc = timed(h, 3, [&] { return launch_fused(P, h->D, rb, pull, parts, h->stream); });
       if (rc) return rc;
     }
     if (h->user.progressive && !h->mesh_complete && !h->nact_pending && h->step % 16 == 0 && h->nact_pinned) {
@@ -929,6 +949,17 @@ int lbm_timing_enable(lbm_t* h, int enable) {
   return LBM_OK;
 }
 
+int lbm_set_split(lbm_t* h, int32_t planes_per_workgroup, int32_t target_workgroups) {
+  if (!h) return LBM_EINVAL;
+  if (planes_per_workgroup != 0 && planes_per_workgroup != 4 && planes_per_workgroup != 8 &&
+      planes_per_workgroup != 16)
+    return fail(h, LBM_EINVAL, "planes_per_workgroup must be 0, 4, 8 or 16 (got %d)", planes_per_workgroup);
+  if (target_workgroups < 1) return fail(h, LBM_EINVAL, "target_workgroups must be positive");
+  h->split_planes = planes_per_workgroup;
+  h->split_target = target_workgroups;
+  return LBM_OK;
+}
+
 int lbm_timing_read(lbm_t* h, int64_t* counts, double* total_ms, int32_t n) {
   if (!h) return LBM_EINVAL;
   int rc = collect_timing(h);
@@ -988,6 +1019,7 @@ struct lbm_batch {
   bool progressive = false;
   bool in_place = false;                          // members use LBM_PATTERN_AA
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
+  int parts = 0;                                 // step-kernel split the graphs were captured with
 };
 
 namespace {
@@ -1062,13 +1094,28 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const int32_t st = (int32_t)h->step;
     HIP_TRY(h, hipMemcpy(h->D.ctrl + kStepCount, &st, sizeof st, hipMemcpyHostToDevice));
+    int32_t na = 0;
+    HIP_TRY(h, hipMemcpy(&na, h->D.ctrl + kNActive, sizeof na, hipMemcpyDeviceToHost));
+    h->n_est = na;
   }
   hipError_t e = launch_batch_offsets(b->B, P0, b->stream);
   int64_t step = h0->step;
   int rbuf = h0->rbuf;
   int32_t k = 0;
+  int n_sum = 0;
+  for (lbm_t* h : b->members) n_sum += h->n_est;
+  const int parts = step_parts(h0->split_planes, h0->split_target, n_sum);
+  if (parts != b->parts) {  // the captured steps were made for another split
+    for (hipGraphExec_t& g : b->graph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    b->parts = parts;
+  }
   auto eager = [&](bool first) {
-    const hipError_t r = launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->in_place, b->stream);
+    const hipError_t r =
+        launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->in_place, parts, b->stream);
     if (r == hipSuccess) {
       rbuf ^= 1;
       step++;
@@ -1082,8 +1129,10 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
     if (!g) {
       hipGraph_t graph = nullptr;
       e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->in_place, b->stream);
-      if (e == hipSuccess) e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->in_place, b->stream);
+      if (e == hipSuccess)
+        e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->in_place, parts, b->stream);
+      if (e == hipSuccess)
+        e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->in_place, parts, b->stream);
       hipError_t ec = hipStreamEndCapture(b->stream, &graph);
       if (e == hipSuccess) e = ec;
       if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);

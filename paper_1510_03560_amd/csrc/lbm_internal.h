@@ -96,6 +96,8 @@ struct Buffers {
   int32_t* block_slot;    // [nb] slot of a block, -1 when inactive
   int32_t* slot_block;    // [capacity] block of a slot (the active list)
   int32_t* order;         // [capacity] the active slots in block order (scheduling order of the step)
+  int32_t* frontier;      // [capacity] nonzero while the slot's block may have an inactive neighbour holding
+                          // fluid (set when the slot is initialised, cleared by the criterion once it has none)
   uint8_t* bfluid;        // [nb] block holds a non-solid cell
   uint8_t* solid;         // [nx*ny*nz] solid flags of the whole lattice
   int32_t* request;       // [nb] activation requests
@@ -133,8 +135,9 @@ hipError_t launch_init_slots(const Params& P, const Buffers& D, int buf, int fir
                              bool from_device_counts, bool use_initial_fields, hipStream_t stream,
                              int mode = kInitNatural, int born = -1);
 hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStream_t stream);
-// Fused step kernel: moments, psi, forces, collision and streaming.
-hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream);
+// Fused step kernel: moments, psi, forces, collision and streaming.  parts
+// (1, 2 or 4) workgroups share each block, each taking 16 / parts planes.
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, int parts, hipStream_t stream);
 // Criterion of Eq 13 and leak checks on the shell cells of frontier blocks.
 enum : int {
   kCritRecord = 1,    // store this step's velocities for the next comparison
@@ -163,7 +166,7 @@ hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, int rd, i
 // component count, mode and step parity.
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream);
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             bool in_place, hipStream_t stream);
+                             bool in_place, int parts, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
 // out[n] = 1 for cells of active blocks (lattice-wide, N bytes).

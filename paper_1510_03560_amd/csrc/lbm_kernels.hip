@@ -571,6 +571,18 @@ __device__ __forceinline__ typename S::T rest_stored(const Params& P, int a, int
     return __ushort_as_half((unsigned short)P.f_rest_bits[a][i]);
 }
 
+// Batched kernels copy their member's Params and Buffers into LDS once per
+// workgroup: read through a reference into global memory, every field would
+// be loaded again after each global store, which the compiler must assume
+// could overwrite it.
+template <typename T>
+__device__ __forceinline__ void stage_struct(T& dst, const T& src) {
+  static_assert(sizeof(T) % 4 == 0, "word copy");
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
+  for (int k = threadIdx.x; k < (int)(sizeof(T) / 4); k += blockDim.x) d[k] = s[k];
+}
+
 // ----------------------------------------------------------- rest state
 // Iterates the update of a cell whose every neighbour is itself (uniform
 // lattice at rest, density bg) until the stored populations (and, for the
@@ -639,27 +651,56 @@ __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) 
 // cell kind), populations of buffer `buf` (placed as `mode` says), psi,
 // reference densities and the criterion history.  Slot `capacity` (the rest
 // slot) is initialised the same way with the rest state everywhere and an
-// all-fluid mask.
+// all-fluid mask.  A workgroup takes a quarter of a slot (1024 cells, four
+// per thread) at a time, so that a handful of new blocks still spreads over
+// many compute units; the stored rest populations come from LDS.
+constexpr int kInitQuarters = 4;
+
 template <typename S>
 __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, int first_h, int count_h, int from_dev,
                                               int use_init, Batch Bt, int mode, int born) {
   // batched: blockIdx.y selects the simulation
   const bool batched = Bt.nsims > 0;
-  const Params& P = batched ? Bt.P[blockIdx.y] : Pv;
-  const Buffers& D = batched ? Bt.D[blockIdx.y] : Dv;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if (batched) {
+    stage_struct(P_s, Bt.P[blockIdx.y]);
+    stage_struct(D_s, Bt.D[blockIdx.y]);
+    __syncthreads();
+  }
+  const Params& P = batched ? P_s : Pv;
+  const Buffers& D = batched ? D_s : Dv;
   const int first = from_dev ? D.ctrl[kNewFirst] : first_h;
   const int count = from_dev ? D.ctrl[kNewCount] : count_h;
+  if (count <= 0) return;  // the same value for the whole workgroup
   if (batched) born = D.ctrl[kStepCount];  // the members' step, kept on the device
+  __shared__ uint32_t rest_bits[kMaxComp][kQ];
+  if (threadIdx.x < kMaxComp * kQ) {
+    const int a = threadIdx.x / kQ, i = threadIdx.x % kQ;
+    rest_bits[a][i] = P.f_rest_bits[a][i];
+  }
+  __syncthreads();
   const uint32_t plane = P.plane;
+  const int ncomp = P.ncomp;
   typename S::T* fb = fplane<S>(D, buf);
   const long long N = (long long)P.nx * P.ny * P.nz;
-  for (int k = blockIdx.x; k < count; k += gridDim.x) {
-    const int slot = first + k;
+  auto stored_rest = [&](int a, int i) -> typename S::T {
+    const uint32_t bits = rest_bits[a][i];
+    if constexpr (std::is_same<typename S::T, float>::value)
+      return __uint_as_float(bits);
+    else
+      return __ushort_as_half((unsigned short)bits);
+  };
+  for (int u = blockIdx.x; u < count * kInitQuarters; u += gridDim.x) {
+    const int slot = first + u / kInitQuarters;
+    const int quarter = u % kInitQuarters;
     const bool rest_slot = slot == P.capacity;
     const int blk = rest_slot ? -1 : D.slot_block[slot];
     const int bx = rest_slot ? 0 : blk % P.nbx, by = rest_slot ? 0 : (blk / P.nbx) % P.nby,
               bz = rest_slot ? 0 : blk / (P.nbx * P.nby);
-    for (int c = threadIdx.x; c < kCells; c += blockDim.x) {
+#pragma unroll 1
+    for (int c = quarter * (kCells / kInitQuarters) + (int)threadIdx.x; c < (quarter + 1) * (kCells / kInitQuarters);
+         c += (int)blockDim.x) {
       int x, y, z;
       cell_xyz(c, x, y, z);
       const uint32_t cid = (uint32_t)slot * kCells + c;
@@ -675,49 +716,59 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
         uint32_t kind = D.solid[n] ? kSolid : kFluid;
         if (kind == kFluid) {
           const bool on[6] = {X == 0, X == P.nx - 1, Y == 0, Y == P.ny - 1, Z == 0, Z == P.nz - 1};
+#pragma unroll
           for (int fc = 0; fc < 6; ++fc)
             if (on[fc] && P.bc[fc] == kOutletFace) kind = kOutlet;
+#pragma unroll
           for (int fc = 0; fc < 6; ++fc)
             if (on[fc] && P.bc[fc] == kInletFace) kind = kInlet;
         }
         m = kind << kKindShift;
-        unroll<kQ>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (i > 0) {
-            int s[3] = {X - dir_ex(i), Y - dir_ey(i), Z - dir_ez(i)};
-            const int L[3] = {P.nx, P.ny, P.nz};
-            bool bounce = false;
-            for (int d = 0; d < 3; ++d) {
-              if (s[d] < 0 || s[d] >= L[d]) {
-                if (P.bc[2 * d] != kPeriodic) bounce = true;
-                s[d] = (s[d] + L[d]) % L[d];
-              }
-            }
-            if (!bounce) bounce = D.solid[s[0] + (long long)P.nx * (s[1] + (long long)P.ny * s[2])] != 0;
-            if (bounce) m |= 1u << i;
+        unroll<kQ - 1>([&](auto I) {
+          constexpr int i = decltype(I)::value + 1;
+          int sx = X - dir_ex(i), sy = Y - dir_ey(i), sz = Z - dir_ez(i);
+          bool bounce = false;
+          if (dir_ex(i) != 0 && (sx < 0 || sx >= P.nx)) {
+            if (P.bc[0] != kPeriodic) bounce = true;
+            sx = (sx + P.nx) % P.nx;
           }
+          if (dir_ey(i) != 0 && (sy < 0 || sy >= P.ny)) {
+            if (P.bc[2] != kPeriodic) bounce = true;
+            sy = (sy + P.ny) % P.ny;
+          }
+          if (dir_ez(i) != 0 && (sz < 0 || sz >= P.nz)) {
+            if (P.bc[4] != kPeriodic) bounce = true;
+            sz = (sz + P.nz) % P.nz;
+          }
+          if (!bounce) bounce = D.solid[sx + (long long)P.nx * (sy + (long long)P.ny * sz)] != 0;
+          if (bounce) m |= 1u << i;
         });
       }
       D.mask[cid] = m;
+      if (c == 0 && !rest_slot) D.frontier[slot] = 1;
       // in place, before an even step: the links whose source cell lies in a
       // block that took part in the last step (active, not joining now)
       // take what that cell streamed towards this one (each such value has
       // one receiving link, so one thread moves it)
       uint32_t stash[kQ];
+#pragma unroll
       for (int i = 0; i < kQ; ++i) stash[i] = ~0u;
       if (mode == kInitStash && !rest_slot && ((m >> kKindShift) & 3u) != kSolid) {
-        for (int i = 1; i < kQ; ++i) {
-          if ((m >> i) & 1u) continue;  // bounced: rest, like every link from a solid cell
-          const int sx = (X - dir_ex(i) + P.nx) % P.nx, sy = (Y - dir_ey(i) + P.ny) % P.ny,
-                    sz = (Z - dir_ez(i) + P.nz) % P.nz;
-          const int nbk = sx / kB + P.nbx * (sy / kB + P.nby * (sz / kB));
-          const int sl = D.block_slot[nbk];
-          if (sl >= 0 && D.act_step[nbk] != born) stash[i] = (uint32_t)sl * kCells + cell_of(sx & 15, sy & 15, sz & 15);
-        }
+        unroll<kQ - 1>([&](auto I) {
+          constexpr int i = decltype(I)::value + 1;
+          if (!((m >> i) & 1u)) {  // bounced: rest, like every link from a solid cell
+            const int sx = (X - dir_ex(i) + P.nx) % P.nx, sy = (Y - dir_ey(i) + P.ny) % P.ny,
+                      sz = (Z - dir_ez(i) + P.nz) % P.nz;
+            const int nbk = sx / kB + P.nbx * (sy / kB + P.nby * (sz / kB));
+            const int sl = D.block_slot[nbk];
+            if (sl >= 0 && D.act_step[nbk] != born)
+              stash[i] = (uint32_t)sl * kCells + cell_of(sx & 15, sy & 15, sz & 15);
+          }
+        });
       }
       if (D.psi)
-        for (int a = 0; a < P.ncomp; ++a) D.psi[(size_t)a * plane + cid] = P.psi_rest[a];
-      for (int a = 0; a < P.ncomp; ++a) {
+        for (int a = 0; a < ncomp; ++a) D.psi[(size_t)a * plane + cid] = P.psi_rest[a];
+      for (int a = 0; a < ncomp; ++a) {
         float r0 = __int_as_float(0x7fc00000);  // NaN: rest state
         float ux = 0.0f, uy = 0.0f, uz = 0.0f;
         if (use_init && n >= 0 && D.init_rho) {
@@ -730,20 +781,24 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
         }
         const bool at_rest = !(r0 == r0);
         float fe[kQ];
-        for (int i = 0; i < kQ; ++i) fe[i] = at_rest ? 0.0f : feq_dir(i, r0, ux, uy, uz);
+        unroll<kQ>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          fe[i] = at_rest ? 0.0f : feq_dir(i, r0, ux, uy, uz);
+        });
         // reference density of the FP16 store: the cell's own density
         const float rref = at_rest ? P.rho_ref_rest[a] : moments(fe).rho;
-        for (int i = 0; i < kQ; ++i) {
-          typename S::T v = at_rest ? rest_stored<S>(P, a, mode == kInitSwapped ? dir_opp(i) : i)
+        unroll<kQ>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          typename S::T v = at_rest ? stored_rest(a, mode == kInitSwapped ? dir_opp(i) : i)
                                     : S::encode(fe[i], dir_w(i) * rref);
           if (stash[i] != ~0u) {
             // moved here; the sender's address reads as the rest state again
             typename S::T* sp = fb + (size_t)(a * kQ + dir_opp(i)) * plane + stash[i];
             v = *sp;
-            *sp = rest_stored<S>(P, a, dir_opp(i));
+            *sp = stored_rest(a, dir_opp(i));
           }
           fb[(size_t)(a * kQ + i) * plane + cid] = v;
-        }
+        });
         if constexpr (S::kRef) {
           D.rho[0][(size_t)a * plane + cid] = rref;
           D.rho[1][(size_t)a * plane + cid] = rref;
@@ -1008,22 +1063,36 @@ constexpr int kPsiRing = 4;
 constexpr int kFoot = kH * kH;  // 324 columns
 
 template <typename S, int NC, bool PULL, bool BATCH>
-__global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, int rbuf, Batch Bt) {
-  int sim = 0, g;
+__global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, int rbuf, Batch Bt, int parts) {
+  // parts workgroups share a block, each sweeping kB / parts of its planes
+  // (plus the two halo planes): more workgroups for a small mesh; the parts
+  // of a block are adjacent in the XCD mapping, so they share one L2
+  int sim = 0, g, part;
   if constexpr (BATCH) {
     const int total = Bt.off[Bt.nsims];
-    const int gi = slot_of_workgroup(blockIdx.x, total);
-    if (gi >= total) return;
-    sim = batch_sim(Bt, gi);
-    g = gi - Bt.off[sim];
+    const int gi = slot_of_workgroup(blockIdx.x, total * parts);
+    if (gi >= total * parts) return;
+    part = gi % parts;
+    sim = batch_sim(Bt, gi / parts);
+    g = gi / parts - Bt.off[sim];
   }
-  const Params& P = BATCH ? Bt.P[sim] : Pv;
-  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if constexpr (BATCH) {
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+  }
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
   if constexpr (!BATCH) {
     const int n_active = D.ctrl[kNActive];
-    g = slot_of_workgroup(blockIdx.x, n_active);
-    if (g >= n_active) return;
+    const int gi = slot_of_workgroup(blockIdx.x, n_active * parts);
+    if (gi >= n_active * parts) return;
+    g = gi / parts;
+    part = gi % parts;
   }
+  const int zlen = kB / parts, z0 = part * zlen;
   const int s = D.order[g];  // active slots in block order
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
@@ -1096,8 +1165,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   auto in_mesh = [&](int z) { return ctx.nslot[dxy + 9 * sgn_out(z)] != P.capacity; };
   constexpr uint32_t kNoCell = (uint32_t)kSolid << kKindShift;
   {
-    const uint32_t raw = mask_load(-1);
-    mask_s[0][t] = in_mesh(-1) ? raw : kNoCell;
+    const uint32_t raw = mask_load(z0 - 1);
+    mask_s[0][t] = in_mesh(z0 - 1) ? raw : kNoCell;
   }
   // references of plane zp: entries t, t + 384, ... of the NC x 400 values
   constexpr int kRefPer = (NC * kRW * kRW + kFusedThreads - 1) / kFusedThreads;
@@ -1123,7 +1192,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   };
   const int rcol = (cy + 2) * kRW + (cx + 2);  // this column in the reference footprint
   if constexpr (S::kRef) {
-    for (int zp = -2; zp <= 0; ++zp) {
+    for (int zp = z0 - 2; zp <= z0; ++zp) {
       float v[kRefPer];
       rref_fetch(zp, v);
       rref_put(zp, v);
@@ -1131,13 +1200,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
     __syncthreads();
   }
 #pragma unroll 1
-  for (int k = 0; k < kH; ++k) {
-    const int z = k - 1;
-    const bool own = interior && z >= 0 && z < kB;
+  for (int k = 0; k < zlen + 2; ++k) {
+    const int z = z0 + k - 1;
+    const bool own = interior && z >= z0 && z < z0 + zlen;
     const uint32_t m = mask_s[k & 1][t];
     const uint32_t m_ahead = mask_load(z + 1);
     float rref_ahead[kRefPer];  // FP16: references of plane z + 2, handed over like the masks
-    if constexpr (S::kRef) rref_fetch(min(z + 2, kB + 1), rref_ahead);
+    if constexpr (S::kRef) rref_fetch(min(z + 2, z0 + zlen + 1), rref_ahead);
     // ---- plane z: pull, moments, psi
     float f[NC][kQ];
     float rho[NC];
@@ -1322,8 +1391,15 @@ template <typename S, int NC, int RD, bool BATCH>
 __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv, int rbuf, Batch Bt) {
   int sim, g;
   if (!workgroup_block<BATCH>(Dv, Bt, sim, g)) return;
-  const Params& P = BATCH ? Bt.P[sim] : Pv;
-  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if constexpr (BATCH) {
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+  }
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
   const int s = D.order[g];
   __shared__ BlockCtx ctx;
   setup_block(P, D, D.slot_block[s], ctx);
@@ -1378,8 +1454,15 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
   constexpr bool kOdd = RD == kRdAAOdd;
   int sim, g;
   if (!workgroup_block<BATCH>(Dv, Bt, sim, g)) return;
-  const Params& P = BATCH ? Bt.P[sim] : Pv;
-  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if constexpr (BATCH) {
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+  }
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
   const int s = D.order[g];
   __shared__ BlockCtx ctx;
   __shared__ float psi_s[kPsiRing][NC][kFoot];
@@ -1553,13 +1636,23 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
     sim = batch_sim(Bt, gi);
     s = gi - Bt.off[sim];
   }
-  const Params& P = BATCH ? Bt.P[sim] : Pv;
-  const Buffers& D = BATCH ? Bt.D[sim] : Dv;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if constexpr (BATCH) {
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+  }
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
   if constexpr (!BATCH) {
     const int n_active = D.ctrl[kNActive];
     s = slot_of_workgroup(blockIdx.x, n_active);
     if (s >= n_active) return;
   }
+  // a block none of whose neighbours is an inactive block holding fluid
+  // stays so (blocks are never deactivated): such slots skip the pass
+  if (!D.frontier[s]) return;  // uniform
   __shared__ BlockCtx ctx;
   __shared__ int expo[27];
   __shared__ uint16_t list[kCells];
@@ -1569,7 +1662,10 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
   const unsigned cand = ctx.cand;
-  if (!cand) return;  // uniform
+  if (!cand) {  // uniform
+    if (threadIdx.x == 0) D.frontier[s] = 0;
+    return;
+  }
   for (int c = threadIdx.x; c < kCells; c += kThreads) {
     int cxx, cyy, czz;
     cell_xyz(c, cxx, cyy, czz);
@@ -1599,6 +1695,15 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
     const uint32_t m = ld(D.mask, cid * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
     if (kind == kSolid) continue;
+    // the previous velocities, loaded before the pulls so that both are in
+    // flight together
+    float u_old[NC][3];
+    if (flags & kCritEval) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u_old[a][d] = D.uprev[(size_t)(a * 3 + d) * plane + cid];
+    }
     // links x -> x + e_i into a non-solid cell of a candidate block
     uint32_t out_links = 0u;
     unroll<kQ - 1>([&](auto I) {
@@ -1657,8 +1762,9 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
           if (flags & kCritEval) {
             float d2 = 0.0f;
             bool diff = false;
+#pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const float dd = u[d] - up[(size_t)d * plane];
+              const float dd = u[d] - u_old[a][d];
               diff = diff || (dd != 0.0f);
               d2 = d2 + dd * dd;
             }
@@ -2070,7 +2176,7 @@ template <typename S, int NC>
 struct InitL {
   static hipError_t launch(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
                            bool use_init, int mode, int born, hipStream_t st) {
-    const int grid = from_dev ? 512 : (count > 0 ? (count < 4096 ? count : 4096) : 1);
+    const int grid = from_dev ? 1024 : (count > 0 ? (count * kInitQuarters < 8192 ? count * kInitQuarters : 8192) : 1);
     hipLaunchKernelGGL((k_init<S>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
                        use_init ? 1 : 0, Batch{}, mode, born);
     return hipGetLastError();
@@ -2091,12 +2197,12 @@ struct DebugL {
 };
 template <typename S, int NC>
 struct FusedL {
-  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t st) {
-    const dim3 g(grid_for(P.capacity)), b(kFusedThreads);
+  static hipError_t launch(const Params& P, const Buffers& D, int rbuf, bool pull, int parts, hipStream_t st) {
+    const dim3 g(grid_for(P.capacity * parts)), b(kFusedThreads);
     if (pull)
-      hipLaunchKernelGGL((k_fused<S, NC, true, false>), g, b, 0, st, P, D, rbuf, Batch{});
+      hipLaunchKernelGGL((k_fused<S, NC, true, false>), g, b, 0, st, P, D, rbuf, Batch{}, parts);
     else
-      hipLaunchKernelGGL((k_fused<S, NC, false, false>), g, b, 0, st, P, D, rbuf, Batch{});
+      hipLaunchKernelGGL((k_fused<S, NC, false, false>), g, b, 0, st, P, D, rbuf, Batch{}, parts);
     return hipGetLastError();
   }
 };
@@ -2159,8 +2265,9 @@ __global__ void k_batch_tick(Batch B) {
 template <typename S, int NC>
 struct BatchL {
   static hipError_t launch(const Params& P0, const Batch& B, int rbuf, bool first, bool progressive,
-                           bool in_place, hipStream_t st) {
-    const dim3 gc(grid_for(B.total_capacity)), bc(kThreads), gf(grid_for(B.total_capacity)), bf(kFusedThreads);
+                           bool in_place, int parts, hipStream_t st) {
+    const dim3 gc(grid_for(B.total_capacity)), bc(kThreads), gf(grid_for(B.total_capacity * parts)),
+        bf(kFusedThreads);
     if (in_place) {
       // the step's index has the parity of rbuf (both flip every step)
       const int rd = first ? kRdOwn : (rbuf ? kRdAAOdd : kRdAAEven);
@@ -2200,9 +2307,9 @@ struct BatchL {
       hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
     }
     if (first)
-      hipLaunchKernelGGL((k_fused<S, NC, false, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B);
+      hipLaunchKernelGGL((k_fused<S, NC, false, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B, parts);
     else
-      hipLaunchKernelGGL((k_fused<S, NC, true, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B);
+      hipLaunchKernelGGL((k_fused<S, NC, true, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B, parts);
     hipLaunchKernelGGL(k_batch_tick, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B);
     return hipGetLastError();
   }
@@ -2279,8 +2386,9 @@ hipError_t launch_activate(const Params& P, const Buffers& D, int step, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, hipStream_t stream) {
-  return dispatch<FusedL>(P, D, rbuf, pull, stream);
+hipError_t launch_fused(const Params& P, const Buffers& D, int rbuf, bool pull, int parts, hipStream_t stream) {
+  if (parts != 1 && parts != 2 && parts != 4) return hipErrorInvalidValue;
+  return dispatch<FusedL>(P, D, rbuf, pull, parts, stream);
 }
 
 hipError_t launch_criterion(const Params& P, const Buffers& D, int rbuf, int rd, int flags,
@@ -2303,8 +2411,9 @@ hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t st
 }
 
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             bool in_place, hipStream_t stream) {
-  return dispatch<BatchL>(P0, B, rbuf, first, progressive, in_place, stream);
+                             bool in_place, int parts, hipStream_t stream) {
+  if (parts != 1 && parts != 2 && parts != 4) return hipErrorInvalidValue;
+  return dispatch<BatchL>(P0, B, rbuf, first, progressive, in_place, parts, stream);
 }
 
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream) {

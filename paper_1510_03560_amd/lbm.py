@@ -61,7 +61,7 @@ class lbm_stats_t(C.Structure):
 _lib = None
 EXPORTS = ["lbm_create", "lbm_set_geometry", "lbm_plan_bytes", "lbm_activate", "lbm_step", "lbm_sync",
            "lbm_moments", "lbm_moments_noalloc", "lbm_moments_device", "lbm_stats", "lbm_trace", "lbm_debug_fields", "lbm_timing_enable",
-           "lbm_timing_read", "lbm_kernel_name", "lbm_destroy", "lbm_last_error"]
+           "lbm_timing_read", "lbm_set_split", "lbm_kernel_name", "lbm_destroy", "lbm_last_error"]
 
 
 def library_path() -> str:
@@ -93,6 +93,7 @@ def load():
     lib.lbm_debug_fields.argtypes = [vp, C.c_int, P(d)]
     lib.lbm_timing_enable.argtypes = [vp, C.c_int]
     lib.lbm_timing_read.argtypes = [vp, P(C.c_int64), P(d), i32]
+    lib.lbm_set_split.argtypes = [vp, i32, i32]
     lib.lbm_kernel_name.argtypes = [i32]
     lib.lbm_kernel_name.restype = C.c_char_p
     lib.lbm_destroy.argtypes = [vp]
@@ -225,6 +226,10 @@ def lbm_timing_read(h, n: int = NUM_KERNELS):
     _check(load().lbm_timing_read(h, _ptr(counts, C.c_int64), _ptr(ms, C.c_double), n), h)
     names = [load().lbm_kernel_name(k).decode() for k in range(n)]
     return {names[k]: (int(counts[k]), float(ms[k])) for k in range(n)}
+
+
+def lbm_set_split(h, planes_per_workgroup: int = 0, target_workgroups: int = 320):
+    _check(load().lbm_set_split(h, int(planes_per_workgroup), int(target_workgroups)), h)
 
 
 def lbm_destroy(h):
