@@ -193,6 +193,28 @@ def mesh_growth(trace: np.ndarray, stats: dict, total_steps: int) -> dict:
     return {"steps": at, "active_blocks": blocks, "bytes_active": [int(b * per_slot) for b in blocks]}
 
 
+def bench_dtype(store: str) -> str:
+    """The arithmetic type of the timed path: FP32 in both storage formats;
+    the FP16-deviation store is named beside it."""
+    return "f32" if store == "f32" else "f32-compute/f16-store"
+
+
+def fluid_cells_over(trace: np.ndarray, fluid_per_block: np.ndarray, t0: int, k: int) -> int:
+    """Fluid cells of the active blocks summed over steps t0 .. t0+k-1 of a
+    progressive run, from its full activation trace (a block recorded at
+    step s takes part from step s on)."""
+    if not len(trace):
+        return 0
+    order = np.argsort(trace[:, 0], kind="stable")
+    steps, gain = trace[order, 0], fluid_per_block[trace[order, 1]]
+    cum = np.cumsum(gain)
+    total = 0
+    for j in range(k):
+        n = int(np.searchsorted(steps, t0 + j, side="right"))
+        total += int(cum[n - 1]) if n else 0
+    return total
+
+
 def fluid_cells_of_active(case, trace, t) -> int:
     """Fluid cells in the blocks active during step t."""
     p = case.params
@@ -446,7 +468,7 @@ def run_proposal(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=192)
     ap.add_argument("--store", choices=["f32", "f16"], default="f32",
@@ -479,8 +501,11 @@ def main():
     ap.add_argument("--batch-sims", type=int, default=48)
     ap.add_argument("--pattern", choices=["ab", "aa"], default="ab",
                     help="population access pattern: two buffers (ab) or one buffer in place (aa)")
-    ap.add_argument("--inplace-steps", type=int, default=2000,
+    ap.add_argument("--inplace-steps", type=int, default=1000,
                     help="steps of the in-place comparison run (0: skip it)")
+    ap.add_argument("--tts-steps", type=int, default=10000,
+                    help="steps of the time-to-solution runs, progressive and static (0: skip them)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotune of the step kernel's work split")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.last))
@@ -502,6 +527,43 @@ def main():
         run_batch(args)
         return
 
+    run_porous(args)
+
+
+def fused_bytes(fluid: int, cells: int, store: str, pattern: int, lbm) -> int:
+    """Algorithmic bytes of one launch of the dominant kernel on a mesh of
+    `cells` active cells of which `fluid` are fluid."""
+    if pattern == lbm.PATTERN_AA:
+        per = INPLACE_COLLIDE_BYTES_PER_FLUID_CELL if store == "f32" else INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16
+    else:
+        per = K2_BYTES_PER_FLUID_CELL if store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
+    return fluid * per + (cells - fluid) * K2_BYTES_PER_SOLID_CELL
+
+
+def tune_split(case, store, pattern, warmup, steps=24, targets=(1, 320, 640)):
+    """Autotune of the step kernel's work split for the progressive run:
+    the growth-phase steps [warmup, warmup + steps) timed for each split
+    target (1 = one workgroup per block), the fastest returned."""
+    import torch
+    from paper_1510_03560_amd import lbm
+    times = {}
+    for tgt in targets:
+        sim = lbm.Simulation(case, progressive=True, store=store, pattern=pattern)
+        lbm.lbm_set_split(sim.h, 0, tgt)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        times[tgt] = e0.elapsed_time(e1) / steps
+        sim.close()
+    best = min(times, key=times.get)
+    return best, {str(k): round(v, 4) for k, v in times.items()}
+
+
+def run_porous(args):
     import torch
     from paper_1510_03560_amd import lbm
     from paper_1510_03560_amd import workloads as W
@@ -516,66 +578,122 @@ def main():
         print("bench: calibration copy of 1 GiB done (3 launches)", file=sys.stderr, flush=True)
         del src, dst
     n = args.size
+    K, Wm = args.steps, args.warmup
+    tts_steps = args.tts_steps
     t_gen = time.time()
-    case = W.porous_injection(n, args.seed, steps=args.warmup + args.steps)
+    case = W.porous_injection(n, args.seed, steps=max(Wm + K, tts_steps))
     print(f"bench: {case.name} porosity {case.info['porosity']:.4f} generated in {time.time() - t_gen:.1f}s",
           file=sys.stderr, flush=True)
-    K, Wm = args.steps, args.warmup
-
     store = lbm.STORE_F32 if args.store == "f32" else lbm.STORE_F16DEV
     pattern = lbm.PATTERN_AA if args.pattern == "aa" else lbm.PATTERN_AB
+    fluid_b = (case.solid.reshape(n // 16, 16, n // 16, 16, n // 16, 16) == 0).sum(axis=(1, 3, 5)).reshape(-1)
 
-    def timed_run(progressive: bool):
+    # autotuned work split of the step kernel (a performance setting only)
+    split_target, split_times = 320, {}
+    if pattern == lbm.PATTERN_AB and not args.no_tune:
+        split_target, split_times = tune_split(case, store, pattern, Wm)
+        print(f"bench: split target {split_target} ({split_times} ms per growth step)", file=sys.stderr, flush=True)
+
+    def timed_run(progressive: bool, steps: int, warm: int, per_kernel: bool = False):
         sim = lbm.Simulation(case, progressive=progressive, store=store, pattern=pattern)
-        sim.step(Wm)
+        lbm.lbm_set_split(sim.h, 0, split_target)
+        sim.step(warm)
         torch.cuda.synchronize()
         st0 = sim.stats()
         tr0 = sim.trace()
-        n_before = st0["n_active"]
+        if per_kernel:
+            lbm.lbm_timing_enable(sim.h, True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        t_wall = time.perf_counter()
         e0.record()
-        sim.step(K)
+        sim.step(steps)
         e1.record()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
         ms = e0.elapsed_time(e1)
+        times = lbm.lbm_timing_read(sim.h) if per_kernel else None
         st = sim.stats()
         tr = sim.trace()
         new = tr[len(tr0):]
-        nact = active_cells_per_step(new, n_before, Wm, K) if progressive else np.full(K, st["n_active"])
-        out = dict(ms=ms, wall=wall, stats=st, active_blocks_per_step=nact, trace=tr)
+        nact = (active_cells_per_step(new, st0["n_active"], warm, steps) if progressive
+                else np.full(steps, st["n_active"]))
+        # fluid cells of the active blocks, summed over the timed steps (every
+        # activation, the first blocks included, is a trace entry)
+        fluid_cells = (fluid_cells_over(tr, fluid_b, warm, steps) if progressive
+                       else int(fluid_b.sum()) * steps)
+        out = dict(ms=ms, stats=st, active_blocks_per_step=nact, trace=tr, times=times, fluid_cells=fluid_cells)
         return sim, out
 
-    sim_p, prog = timed_run(True)
+    sim_p, prog = timed_run(True, K, Wm)
     print(f"bench: progressive {K} steps {prog['ms']:.1f} ms, blocks {prog['stats']['n_active']}"
           f"/{prog['stats']['n_fluid_blocks']}, leak {prog['stats']['leak']}", file=sys.stderr, flush=True)
     if prog["stats"]["numeric_error"]:
         print("bench: numeric error in the progressive run", file=sys.stderr)
     sim_p.close()
-    sim_s, stat = timed_run(False)
+    sim_s, stat = timed_run(False, K, Wm)
     print(f"bench: static {K} steps {stat['ms']:.1f} ms", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel on the full mesh: per-kernel HIP events
     lbm.lbm_timing_enable(sim_s.h, True)
-    kprof_steps = min(K, 200)
-    sim_s.step(kprof_steps)
+    sim_s.step(min(max(K, 50), 200))
     times = lbm.lbm_timing_read(sim_s.h)
     lbm.lbm_timing_enable(sim_s.h, False)
     sim_s.close()
     dominant = "inplace_collide" if pattern == lbm.PATTERN_AA else "fused_step"
     cnt, tot = times[dominant]
     k2_ms = tot / max(cnt, 1)
-    fluid_full = fluid_cells_of_active(case.static_twin(), np.zeros((0, 2), np.int32), 0)
+    fluid_full = int(fluid_b.sum())
     cells_full = stat["stats"]["n_active"] * 4096
-    if pattern == lbm.PATTERN_AA:
-        per_fluid = (INPLACE_COLLIDE_BYTES_PER_FLUID_CELL if args.store == "f32"
-                     else INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16)
-    else:
-        per_fluid = K2_BYTES_PER_FLUID_CELL if args.store == "f32" else K2_BYTES_PER_FLUID_CELL_F16
-    k2_bytes = fluid_full * per_fluid + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL
+    k2_bytes = fused_bytes(fluid_full, cells_full, args.store, pattern, lbm)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
+
+    # the growth phase of the timed steps, kernel by kernel (a separate run
+    # with HIP events around every launch, which the timed run does without)
+    sim_g, grow = timed_run(True, K, Wm, per_kernel=True)
+    sim_g.close()
+    growth = {
+        "steps": [Wm, Wm + K],
+        "ms_per_step_with_events": round(grow["ms"] / K, 4),
+        "us_per_step": {k: round(v[1] / K * 1e3, 2) for k, v in grow["times"].items() if v[0]},
+        "launches": {k: v[0] for k, v in grow["times"].items() if v[0]},
+    }
+
+    # time to solution: the whole progressive run against the static mesh
+    # (the two give the same bits, hence the same density error)
+    tts = None
+    if tts_steps > 0:
+        res_f = {}
+        for progressive in (True, False):
+            sim = lbm.Simulation(case, progressive=progressive, store=store, pattern=pattern)
+            lbm.lbm_set_split(sim.h, 0, split_target)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(tts_steps)
+            e1.record()
+            torch.cuda.synchronize()
+            rho = torch.empty(2 * case.N, dtype=torch.float32, device="cuda")
+            lbm.lbm_moments_device(sim.h, rho.data_ptr(), 0, 0)
+            st = sim.stats()
+            tr = sim.trace()
+            sim.close()
+            torch.cuda.synchronize()
+            nact = active_cells_per_step(tr, 0, 0, tts_steps) if progressive else np.full(tts_steps, st["n_active"])
+            res_f[progressive] = dict(ms=e0.elapsed_time(e1), rho=rho, st=st, cells=int(nact.sum()) * 4096)
+            print(f"bench: time to solution, {'progressive' if progressive else 'static'} {tts_steps} steps "
+                  f"{res_f[progressive]['ms']:.0f} ms", file=sys.stderr, flush=True)
+        p_, s_ = res_f[True], res_f[False]
+        tts = {
+            "steps": tts_steps,
+            "progressive_s": round(p_["ms"] * 1e-3, 4),
+            "static_s": round(s_["ms"] * 1e-3, 4),
+            "progressive_over_static": round(p_["ms"] / s_["ms"], 4),
+            "fields_bit_identical": bool(torch.equal(p_["rho"], s_["rho"])),
+            "leak": int(p_["st"]["leak"]),
+            "progressive_active_cell_mlups": round(p_["cells"] / (p_["ms"] * 1e-3) / 1e6, 2),
+            "static_active_cell_mlups": round(s_["cells"] / (s_["ms"] * 1e-3) / 1e6, 2),
+            "domain_mlups_eq16": round(case.N * tts_steps / (p_["ms"] * 1e-3) / 1e6, 2),
+        }
+        del res_f
 
     # the in-place pattern on the same full mesh (half the population memory)
     inplace = None
@@ -599,8 +717,7 @@ def main():
         col_ms = t_a["inplace_collide"][1] / max(t_a["inplace_collide"][0], 1)
         psi_ms = t_a["inplace_psi"][1] / max(t_a["inplace_psi"][0], 1)
         f32 = args.store == "f32"
-        col_bytes = (fluid_full * (INPLACE_COLLIDE_BYTES_PER_FLUID_CELL if f32 else INPLACE_COLLIDE_BYTES_PER_FLUID_CELL_F16)
-                     + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
+        col_bytes = fused_bytes(fluid_full, cells_full, args.store, lbm.PATTERN_AA, lbm)
         psi_bytes = (fluid_full * (INPLACE_PSI_BYTES_PER_FLUID_CELL if f32 else INPLACE_PSI_BYTES_PER_FLUID_CELL_F16)
                      + (cells_full - fluid_full) * K2_BYTES_PER_SOLID_CELL)
         inplace = {
@@ -645,7 +762,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.store == "f32" else "f32-compute/f16-store",
+        "dtype": bench_dtype(args.store),
         "data": "synthetic",
         "config": {
             "workload": f"porous injection {n}^3, 16^3 blocks, spheres r 4-12, porosity "
@@ -658,13 +775,17 @@ def main():
             "active_blocks_start": int(prog["active_blocks_per_step"][0]),
             "active_blocks_end": int(prog["active_blocks_per_step"][-1]),
             "fluid_blocks": int(prog["stats"]["n_fluid_blocks"]),
+            "split_target": split_target,
         },
+        "fluid_cell_mlups": round(prog["fluid_cells"] / (prog["ms"] * 1e-3) / 1e6, 2),
         "domain_mlups_eq16": round(domain_cells / (prog["ms"] * 1e-3) / 1e6, 2),
         "static_ms_per_step": round(stat["ms"] / K, 4),
         "progressive_over_static_time": round(prog["ms"] / stat["ms"], 4),
         "static_active_cell_mlups": round(cells_full * K / (stat["ms"] * 1e-3) / 1e6, 2),
         "leak": int(prog["stats"]["leak"]),
         "mesh_growth": mesh_growth(prog["trace"], prog["stats"], Wm + K),
+        "growth_phase": growth,
+        "split_tuning_ms_per_step": split_times,
         "kernel_ms_per_launch": {k: round(v[1] / max(v[0], 1), 5) for k, v in times.items()},
         "roofline": {
             "kernel": dominant,
@@ -680,6 +801,8 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
     }
+    if tts is not None:
+        res["time_to_solution"] = tts
     if inplace is not None:
         res["inplace"] = inplace
     if not args.no_cpu:

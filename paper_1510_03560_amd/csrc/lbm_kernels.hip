@@ -656,20 +656,20 @@ __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) 
 // many compute units; the stored rest populations come from LDS.
 constexpr int kInitQuarters = 4;
 
-template <typename S>
+template <typename S, bool BATCH>
 __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, int first_h, int count_h, int from_dev,
                                               int use_init, Batch Bt, int mode, int born) {
   // batched: blockIdx.y selects the simulation
-  const bool batched = Bt.nsims > 0;
+  constexpr bool batched = BATCH;
   __shared__ Params P_s;
   __shared__ Buffers D_s;
-  if (batched) {
+  if constexpr (BATCH) {
     stage_struct(P_s, Bt.P[blockIdx.y]);
     stage_struct(D_s, Bt.D[blockIdx.y]);
     __syncthreads();
   }
-  const Params& P = batched ? P_s : Pv;
-  const Buffers& D = batched ? D_s : Dv;
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
   const int first = from_dev ? D.ctrl[kNewFirst] : first_h;
   const int count = from_dev ? D.ctrl[kNewCount] : count_h;
   if (count <= 0) return;  // the same value for the whole workgroup
@@ -2177,7 +2177,7 @@ struct InitL {
   static hipError_t launch(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
                            bool use_init, int mode, int born, hipStream_t st) {
     const int grid = from_dev ? 1024 : (count > 0 ? (count * kInitQuarters < 8192 ? count * kInitQuarters : 8192) : 1);
-    hipLaunchKernelGGL((k_init<S>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
+    hipLaunchKernelGGL((k_init<S, false>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
                        use_init ? 1 : 0, Batch{}, mode, born);
     return hipGetLastError();
   }
@@ -2282,7 +2282,7 @@ struct BatchL {
                                     : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
             hipLaunchKernelGGL((k_criterion<S, NC, M, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
             hipLaunchKernelGGL((k_activate<true>), dim3(B.nsims), dim3(1024), 0, st, P0, Buffers{}, 0, B);
-            hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
+            hipLaunchKernelGGL((k_init<S, true>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
                                mode, -1);
             hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
           }
@@ -2302,7 +2302,7 @@ struct BatchL {
       else
         hipLaunchKernelGGL((k_criterion<S, NC, kRdPull, true>), gc, bc, 0, st, P0, Buffers{}, rbuf, flags, B);
       hipLaunchKernelGGL((k_activate<true>), dim3(B.nsims), dim3(1024), 0, st, P0, Buffers{}, 0, B);
-      hipLaunchKernelGGL((k_init<S>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
+      hipLaunchKernelGGL((k_init<S, true>), dim3(64, B.nsims), dim3(256), 0, st, P0, Buffers{}, rbuf, 0, 0, 1, 0, B,
                          (int)kInitNatural, -1);
       hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
     }

@@ -88,3 +88,18 @@ def test_mesh_growth_counts_blocks_by_activation_step():
     assert g["steps"][-1] == 100 and g["bytes_active"][-1] == 600
     empty = bench.mesh_growth(np.zeros((0, 2), np.int32), {"bytes_active": 0, "n_active": 0}, 10)
     assert empty["active_blocks"] == [0] * len(empty["steps"])
+
+
+def test_dtype_names_the_store():
+    assert bench.bench_dtype("f32") == "f32"
+    assert bench.bench_dtype("f16") == "f32-compute/f16-store"
+
+
+def test_fluid_cells_over_trace():
+    """Blocks count from the step their trace entry names: initial blocks at
+    step 0, later ones from their activation step on."""
+    fluid = np.array([100, 50, 0, 7])
+    trace = np.array([[0, 0], [0, 1], [3, 3]], dtype=np.int32)
+    # steps 2, 3, 4: 150, 157, 157
+    assert bench.fluid_cells_over(trace, fluid, 2, 3) == 150 + 157 + 157
+    assert bench.fluid_cells_over(np.zeros((0, 2), np.int32), fluid, 0, 4) == 0
