@@ -1712,8 +1712,23 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
       const bool target_solid = (m >> dir_opp(i)) & 1u;  // x + e_i solid or outside
       if (d != 13 && ((cand >> d) & 1u) && !target_solid) out_links |= 1u << i;
     });
+    // every load of the cell is issued before any is used: the pulled
+    // populations, then (for the leak check) the populations this cell
+    // stored last step, all of its 18 links, so that no load waits behind
+    // a branch of its own
+    float f[NC][kQ];
+    if (pull_cells) {
+      PullAxes pa;
+      pull_axes_xy(x, y, pa);
+      pull_axes_z(z, pa);
+      Sources<S::kRef> src;
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) gather<S>(fb, plane, a, src, rref, f[a]);
+    }
     uint32_t bad = 0u;  // failing links
     if ((flags & kCritEmission) && out_links) {
+      uint32_t em[NC][kQ];
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         unroll<kQ - 1>([&](auto I) {
@@ -1722,30 +1737,27 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
           // f*_i(x) is stored at (x, plane i), or with the in-place pattern
           // at (x, opposite plane) after either parity of step
           constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
-          if ((out_links >> i) & 1u) {
-            const typename S::T v = ld(fb + (size_t)(a * kQ + first) * plane,
-                                       (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(typename S::T));
-            if (S::bits(v) != P.f_rest_bits[a][i]) bad |= 1u << i;
-          }
+          em[a][i] = S::bits(ld(fb + (size_t)(a * kQ + first) * plane,
+                                (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(typename S::T)));
+        });
+        if constexpr (S::kRef) em[a][0] = __float_as_uint(ld(rref + (size_t)a * plane, cid * 4u));
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        unroll<kQ - 1>([&](auto I) {
+          constexpr int i = decltype(I)::value + 1;
+          if (((out_links >> i) & 1u) && em[a][i] != P.f_rest_bits[a][i]) bad |= 1u << i;
         });
         if constexpr (S::kRef) {
-          if (__float_as_uint(ld(rref + (size_t)a * plane, cid * 4u)) != __float_as_uint(P.rho_ref_rest[a]))
-            bad = out_links;
+          if (em[a][0] != __float_as_uint(P.rho_ref_rest[a])) bad = out_links;
         }
       }
     }
     if (pull_cells) {
-      PullAxes pa;
-      pull_axes_xy(x, y, pa);
-      pull_axes_z(z, pa);
-      Sources<S::kRef> src;
-      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
       bool changed = false, psi_differs = false;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
-        const Mom mo = moments(f);
+        const Mom mo = moments(f[a]);
         float psi = P.psi_rest[a];
         if (kind == kFluid) {
           bool cl;
