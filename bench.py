@@ -296,83 +296,131 @@ def run_channels(args):
 
 
 def batch_cases(args):
-    """Many small progressive porous-injection runs: lattice sides drawn from
-    32..128 in steps of 16, porosity uniform in [0.5, 0.8], one seed each."""
+    """Many small progressive porous-injection runs: each lattice side drawn
+    uniformly from 24..128 (sides that are not whole blocks are padded with
+    solid cells), porosity uniform in [0.5, 0.8], one seed each."""
     from paper_1510_03560_amd import workloads as W
     rng = np.random.Generator(np.random.PCG64(args.seed))
     cases = []
     for k in range(args.batch_sims):
-        shape = tuple(int(v) for v in 16 * rng.integers(2, 9, size=3))
+        shape = tuple(int(v) for v in rng.integers(24, 129, size=3))
         cases.append(W.porous_injection(0, seed=1000 + k, porosity=float(rng.uniform(0.5, 0.8)), shape=shape))
     return cases
 
 
+BATCH_CONFIGS = [(False, 1), (False, 640), (True, 1), (True, 640)]  # (persistent, split target)
+
+
 def run_batch(args):
     """Batched stepping: the same set of small simulations advanced (a) one
-    handle after another with lbm_step, (b) as one batch launching each step
-    eagerly, (c) as one batch replaying captured graphs.  Time is wall clock
-    between device-wide synchronisations (the batch runs on its own stream);
-    final states are compared bit for bit through the mass and counters."""
+    handle after another with lbm_step, (b) as one batch replaying captured
+    graphs, its schedule autotuned first: the step kernel one workgroup per
+    item or persistent (work taking), and the work split (planes per
+    workgroup), each timed on the batch itself and the fastest kept.  Both
+    time the same steps; wall clock between device-wide synchronisations (the
+    batch runs on its own stream); final states compared bit for bit through
+    the mass and counters."""
     import torch
     from paper_1510_03560_amd import batch, lbm
 
     torch.cuda.set_device(0)
     cases = batch_cases(args)
     K, Wm = args.steps, args.warmup
+    # the configurations are timed in turn on short slices of the same run,
+    # several rounds, so that each sees the mesh at about the same stage
+    tune_steps, rounds = 6, 6
+    skip = Wm + tune_steps * rounds * len(BATCH_CONFIGS)
     print(f"bench: batch of {len(cases)} cases generated, {sum(c.N for c in cases) / 1e6:.2f} M cells",
           file=sys.stderr, flush=True)
-    out = {}
-    for mode in ("alone", "batch_eager", "batch_graph"):
-        sims = [lbm.Simulation(c) for c in cases]
-        b = batch.Batch(sims) if mode != "alone" else None
 
-        def advance(n):
-            if b is None:
-                for s_ in sims:
-                    s_.step(n)
-            else:
-                b.step(n, use_graph=(mode == "batch_graph"))
-
-        advance(Wm)
-        torch.cuda.synchronize()
-        n0 = [s_.stats()["n_active"] for s_ in sims]
-        tr0 = [len(s_.trace()) for s_ in sims]
-        t0 = time.perf_counter()
-        advance(K)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        cells = 0
-        finals = []
-        for s_, a, l0 in zip(sims, n0, tr0):
-            new = s_.trace()[l0:]
-            cells += 4096 * int(active_cells_per_step(new, a, Wm, K).sum())
-            st = s_.stats()
-            finals.append((st["n_active"], st["activations"], st["leak"], tuple(st["mass"])))
-        if b is not None:
-            b.close()
+    def finals_of(sims):
+        """Per member: counters and a digest of the density fields' bits."""
+        import hashlib
+        out = []
         for s_ in sims:
-            s_.close()
-        out[mode] = dict(wall=wall, cells=cells, finals=finals)
-        print(f"bench: batch mode {mode}: {K} steps in {wall * 1e3:.1f} ms, "
-              f"{cells / wall / 1e6:.1f} active-cell MLUPS", file=sys.stderr, flush=True)
-    g = out["batch_graph"]
+            st = s_.stats()
+            rho = torch.empty(s_.ncomp * s_.N, dtype=torch.float32, device="cuda")
+            lbm.lbm_moments_device(s_.h, rho.data_ptr(), 0, 0)
+            torch.cuda.synchronize()
+            digest = hashlib.sha256(rho.cpu().numpy().tobytes()).hexdigest()
+            out.append((st["n_active"], st["activations"], st["leak"], digest))
+        return out
+
+    def cells_of(sims, n0, tr0, t0, k):
+        cells = 0
+        for s_, a, l0 in zip(sims, n0, tr0):
+            cells += 4096 * int(active_cells_per_step(s_.trace()[l0:], a, t0, k).sum())
+        return cells
+
+    # (a) one handle after another
+    sims = [lbm.Simulation(c) for c in cases]
+    for s_ in sims:
+        s_.step(skip)
+    torch.cuda.synchronize()
+    n0 = [s_.stats()["n_active"] for s_ in sims]
+    tr0 = [len(s_.trace()) for s_ in sims]
+    t0 = time.perf_counter()
+    for s_ in sims:
+        s_.step(K)
+    torch.cuda.synchronize()
+    wall_alone = time.perf_counter() - t0
+    cells_alone = cells_of(sims, n0, tr0, skip, K)
+    finals_alone = finals_of(sims)
+    for s_ in sims:
+        s_.close()
+    print(f"bench: batch mode alone: {K} steps in {wall_alone * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # (b) the batch: autotune the schedule on the batch itself, then time
+    sims = [lbm.Simulation(c) for c in cases]
+    b = batch.Batch(sims)
+    b.step(Wm, use_graph=True)
+    tuning = {f"persistent={int(p)},target={t}": [] for p, t in BATCH_CONFIGS}
+    for _ in range(rounds):
+        for p, t in BATCH_CONFIGS:
+            lbm.lbm_set_split(sims[0].h, 0, t)
+            b.schedule(p)
+            b.step(2, use_graph=True)  # capture the graphs outside the timed steps
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.step(tune_steps - 2, use_graph=True)
+            torch.cuda.synchronize()
+            tuning[f"persistent={int(p)},target={t}"].append((time.perf_counter() - t0) * 1e3 / (tune_steps - 2))
+    best = min(BATCH_CONFIGS, key=lambda c: sum(tuning[f"persistent={int(c[0])},target={c[1]}"]))
+    lbm.lbm_set_split(sims[0].h, 0, best[1])
+    b.schedule(best[0])
+    print(f"bench: batch schedule persistent={best[0]} target={best[1]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    n0 = [s_.stats()["n_active"] for s_ in sims]
+    tr0 = [len(s_.trace()) for s_ in sims]
+    t0 = time.perf_counter()
+    b.step(K, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = cells_of(sims, n0, tr0, skip, K)
+    finals = finals_of(sims)
+    b.close()
+    for s_ in sims:
+        s_.close()
+    print(f"bench: batch mode graph: {K} steps in {wall * 1e3:.1f} ms, {cells / wall / 1e6:.1f} active-cell MLUPS",
+          file=sys.stderr, flush=True)
     res = {
         "metric": "active-cell MLUPS",
-        "value": round(g["cells"] / g["wall"] / 1e6, 2),
+        "value": round(cells / wall / 1e6, 2),
         "unit": "MLUPS",
-        "n_gpus": 1, "steps": K, "warmup": Wm,
-        "ms_per_step": round(g["wall"] * 1e3 / K, 4),
+        "n_gpus": 1, "steps": K, "warmup": skip,
+        "ms_per_step": round(wall * 1e3 / K, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batch of {len(cases)} progressive porous-injection runs, sides 32-128, "
-                               f"porosity 0.5-0.8, FP32, graph replay",
+        "config": {"workload": f"batch of {len(cases)} progressive porous-injection runs, sides 24-128, "
+                               f"porosity 0.5-0.8, FP32, graph replay, autotuned schedule",
                    "shapes": [[c.params["nx"], c.params["ny"], c.params["nz"]] for c in cases],
-                   "seed": args.seed},
-        "alone_ms_per_step": round(out["alone"]["wall"] * 1e3 / K, 4),
-        "batch_eager_ms_per_step": round(out["batch_eager"]["wall"] * 1e3 / K, 4),
-        "speedup_graph_over_alone": round(out["alone"]["wall"] / g["wall"], 3),
-        "identical_to_alone": bool(all(out[m]["finals"] == out["alone"]["finals"]
-                                       for m in ("batch_eager", "batch_graph"))),
+                   "cells": int(sum(c.N for c in cases)), "seed": args.seed},
+        "schedule": {"persistent": bool(best[0]), "split_target": best[1],
+                     "tuning_ms_per_step": {k: [round(v, 4) for v in vs] for k, vs in tuning.items()}},
+        "alone_ms_per_step": round(wall_alone * 1e3 / K, 4),
+        "alone_active_cell_mlups": round(cells_alone / wall_alone / 1e6, 2),
+        "speedup_over_alone": round(wall_alone / wall, 3),
+        "identical_to_alone": bool(finals == finals_alone),
     }
     print(json.dumps(res), flush=True)
 

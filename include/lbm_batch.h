@@ -43,6 +43,15 @@ int lbm_batch_create(lbm_t* const* handles, int32_t n, lbm_batch_t** out);
  * steps enqueued before the failure; the message is on the first member). */
 int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph);
 
+/* Schedule of the step kernel (a performance setting; the results are the
+ * same bits either way).  persistent = 0 (the default): one workgroup per
+ * (block, part) item of the merged active list.  persistent = 1: a resident
+ * grid (as many workgroups as the GPU holds at once) whose workgroups take
+ * items from one queue per XCD, their own first, then steal from the
+ * others, until every queue is empty.  Applies to the two-buffer pattern;
+ * the work split is the first member's (lbm_set_split).  Errors: LBM_EINVAL. */
+int lbm_batch_schedule(lbm_batch_t* b, int32_t persistent);
+
 /* Releases the batch (not the members); waits for its work. */
 int lbm_batch_destroy(lbm_batch_t* b);
 

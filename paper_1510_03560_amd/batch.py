@@ -6,7 +6,7 @@ import ctypes as C
 
 from . import lbm as L
 
-EXPORTS = ["lbm_batch_create", "lbm_batch_step", "lbm_batch_destroy"]
+EXPORTS = ["lbm_batch_create", "lbm_batch_step", "lbm_batch_schedule", "lbm_batch_destroy"]
 
 _ready = False
 
@@ -18,6 +18,7 @@ def _lib():
         vp, i32 = C.c_void_p, C.c_int32
         lib.lbm_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
         lib.lbm_batch_step.argtypes = [vp, i32, i32]
+        lib.lbm_batch_schedule.argtypes = [vp, i32]
         lib.lbm_batch_destroy.argtypes = [vp]
         for n in EXPORTS:
             getattr(lib, n).restype = C.c_int
@@ -38,6 +39,10 @@ def lbm_batch_step(b, nsteps: int, use_graph: bool = True, h_err=None):
     L._check(rc, h_err)
 
 
+def lbm_batch_schedule(b, persistent: bool):
+    L._check(_lib().lbm_batch_schedule(b, 1 if persistent else 0), None)
+
+
 def lbm_batch_destroy(b):
     if b is not None and b.value:
         _lib().lbm_batch_destroy(b)
@@ -51,6 +56,9 @@ class Batch:
         if len({id(s) for s in self.sims}) != len(self.sims):
             raise ValueError("a simulation appears twice in the batch")
         self.b = lbm_batch_create([s.h for s in self.sims])
+
+    def schedule(self, persistent: bool):
+        lbm_batch_schedule(self.b, persistent)
 
     def step(self, n: int = 1, use_graph: bool = True):
         lbm_batch_step(self.b, n, use_graph, self.sims[0].h)

@@ -1020,6 +1020,9 @@ struct lbm_batch {
   bool in_place = false;                          // members use LBM_PATTERN_AA
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting at buffer parity 0 / 1
   int parts = 0;                                 // step-kernel split the graphs were captured with
+  int32_t* heads = nullptr;                      // [8] queue heads of the persistent step kernel
+  bool persistent = false;                       // step kernel as a resident work-taking grid
+  bool graph_persistent = false;                 // schedule the graphs were captured with
 };
 
 namespace {
@@ -1065,13 +1068,15 @@ int lbm_batch_create(lbm_t* const* hs, int32_t n, lbm_batch_t** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&b->P_dev, sizeof(Params) * n);
   if (e == hipSuccess) e = hipMalloc((void**)&b->D_dev, sizeof(Buffers) * n);
   if (e == hipSuccess) e = hipMalloc((void**)&b->off_dev, sizeof(int32_t) * (n + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->heads, sizeof(int32_t) * 8);
+  if (e == hipSuccess) e = hipMemset(b->heads, 0, sizeof(int32_t) * 8);
   if (e == hipSuccess) e = hipMemcpy(b->P_dev, P.data(), sizeof(Params) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->D_dev, D.data(), sizeof(Buffers) * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     lbm_batch_destroy(b);
     return batch_fail("batch create", e);
   }
-  b->B = Batch{b->P_dev, b->D_dev, b->off_dev, n, total};
+  b->B = Batch{b->P_dev, b->D_dev, b->off_dev, n, total, b->heads};
   *out = b;
   return LBM_OK;
 }
@@ -1105,17 +1110,18 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
   int n_sum = 0;
   for (lbm_t* h : b->members) n_sum += h->n_est;
   const int parts = step_parts(h0->split_planes, h0->split_target, n_sum);
-  if (parts != b->parts) {  // the captured steps were made for another split
+  if (parts != b->parts || b->persistent != b->graph_persistent) {  // captured for another schedule
     for (hipGraphExec_t& g : b->graph)
       if (g) {
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
     b->parts = parts;
+    b->graph_persistent = b->persistent;
   }
   auto eager = [&](bool first) {
     const hipError_t r =
-        launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->in_place, parts, b->stream);
+        launch_batch_step(b->B, P0, rbuf, first, b->progressive, b->in_place, parts, b->persistent, b->stream);
     if (r == hipSuccess) {
       rbuf ^= 1;
       step++;
@@ -1130,9 +1136,10 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
       hipGraph_t graph = nullptr;
       e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess)
-        e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->in_place, parts, b->stream);
+        e = launch_batch_step(b->B, P0, rbuf, false, b->progressive, b->in_place, parts, b->persistent, b->stream);
       if (e == hipSuccess)
-        e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->in_place, parts, b->stream);
+        e = launch_batch_step(b->B, P0, rbuf ^ 1, false, b->progressive, b->in_place, parts, b->persistent,
+                              b->stream);
       hipError_t ec = hipStreamEndCapture(b->stream, &graph);
       if (e == hipSuccess) e = ec;
       if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
@@ -1160,6 +1167,12 @@ int lbm_batch_step(lbm_batch_t* b, int32_t nsteps, int32_t use_graph) {
   return LBM_OK;
 }
 
+int lbm_batch_schedule(lbm_batch_t* b, int32_t persistent) {
+  if (!b || (persistent != 0 && persistent != 1)) return LBM_EINVAL;
+  b->persistent = persistent != 0;
+  return LBM_OK;
+}
+
 int lbm_batch_destroy(lbm_batch_t* b) {
   if (!b) return LBM_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1168,6 +1181,7 @@ int lbm_batch_destroy(lbm_batch_t* b) {
   if (b->P_dev) (void)hipFree(b->P_dev);
   if (b->D_dev) (void)hipFree(b->D_dev);
   if (b->off_dev) (void)hipFree(b->off_dev);
+  if (b->heads) (void)hipFree(b->heads);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;

@@ -121,6 +121,7 @@ struct Batch {
   int32_t* off;
   int32_t nsims;
   int32_t total_capacity;
+  int32_t* heads;  // [8] queue heads of the persistent step kernel (one queue per XCD), zero between steps
 };
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the
@@ -165,8 +166,10 @@ hipError_t launch_propose(const Params& P, const Buffers& D, int rbuf, int rd, i
 // of a run (populations read in place).  Every member must share store,
 // component count, mode and step parity.
 hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t stream);
+// persistent: the step kernel as a resident grid taking work items (A-B
+// pattern; the in-place kernels always use one workgroup per item).
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             bool in_place, int parts, hipStream_t stream);
+                             bool in_place, int parts, bool persistent, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
 // out[n] = 1 for cells of active blocks (lattice-wide, N bytes).

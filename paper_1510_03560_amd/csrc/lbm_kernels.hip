@@ -1062,36 +1062,11 @@ constexpr int kFusedThreads = 384;
 constexpr int kPsiRing = 4;
 constexpr int kFoot = kH * kH;  // 324 columns
 
-template <typename S, int NC, bool PULL, bool BATCH>
-__global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, int rbuf, Batch Bt, int parts) {
-  // parts workgroups share a block, each sweeping kB / parts of its planes
-  // (plus the two halo planes): more workgroups for a small mesh; the parts
-  // of a block are adjacent in the XCD mapping, so they share one L2
-  int sim = 0, g, part;
-  if constexpr (BATCH) {
-    const int total = Bt.off[Bt.nsims];
-    const int gi = slot_of_workgroup(blockIdx.x, total * parts);
-    if (gi >= total * parts) return;
-    part = gi % parts;
-    sim = batch_sim(Bt, gi / parts);
-    g = gi / parts - Bt.off[sim];
-  }
-  __shared__ Params P_s;
-  __shared__ Buffers D_s;
-  if constexpr (BATCH) {
-    stage_struct(P_s, Bt.P[sim]);
-    stage_struct(D_s, Bt.D[sim]);
-    __syncthreads();
-  }
-  const Params& P = BATCH ? P_s : Pv;
-  const Buffers& D = BATCH ? D_s : Dv;
-  if constexpr (!BATCH) {
-    const int n_active = D.ctrl[kNActive];
-    const int gi = slot_of_workgroup(blockIdx.x, n_active * parts);
-    if (gi >= n_active * parts) return;
-    g = gi / parts;
-    part = gi % parts;
-  }
+// The work of one workgroup: planes [z0, z0 + 16/parts) of the block in
+// position g of the active list (with the halo planes on either side).
+template <typename S, int NC, bool PULL>
+__device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, int rbuf, int g, int part,
+                                            int parts) {
   const int zlen = kB / parts, z0 = part * zlen;
   const int s = D.order[g];  // active slots in block order
   __shared__ BlockCtx ctx;
@@ -1335,6 +1310,81 @@ __global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, 
   }
   if (numeric) atomicOr(&D.ctrl[kNumeric], 1);
   if (clamps) atomicAdd(&D.counters[1], (unsigned long long)clamps);
+}
+
+template <typename S, int NC, bool PULL, bool BATCH>
+__global__ void __launch_bounds__(kFusedThreads) k_fused(Params Pv, Buffers Dv, int rbuf, Batch Bt, int parts) {
+  // parts workgroups share a block, each sweeping kB / parts of its planes
+  // (plus the two halo planes): more workgroups for a small mesh; the parts
+  // of a block are adjacent in the XCD mapping, so they share one L2
+  int sim = 0, g, part;
+  if constexpr (BATCH) {
+    const int total = Bt.off[Bt.nsims];
+    const int gi = slot_of_workgroup(blockIdx.x, total * parts);
+    if (gi >= total * parts) return;
+    part = gi % parts;
+    sim = batch_sim(Bt, gi / parts);
+    g = gi / parts - Bt.off[sim];
+  }
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  if constexpr (BATCH) {
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+  }
+  const Params& P = BATCH ? P_s : Pv;
+  const Buffers& D = BATCH ? D_s : Dv;
+  if constexpr (!BATCH) {
+    const int n_active = D.ctrl[kNActive];
+    const int gi = slot_of_workgroup(blockIdx.x, n_active * parts);
+    if (gi >= n_active * parts) return;
+    g = gi / parts;
+    part = gi % parts;
+  }
+  fused_block<S, NC, PULL>(P, D, rbuf, g, part, parts);
+}
+
+// Persistent form of the batched step kernel: a resident grid whose
+// workgroups take (block, part) items from the merged active list of all
+// members until none is left.  The list is cut into one contiguous queue per
+// XCD (neighbouring blocks share its L2); a workgroup drains the queue of its
+// own XCD first, then steals from the others.  The queue heads are counters
+// in device memory, reset by the step's closing k_batch_tick; a workgroup
+// stops once every queue is empty, so the grid drains without any
+// workgroup waiting on another.
+__device__ __forceinline__ int take_item(int32_t* heads, int xcd, int total) {
+  const int chunk = (total + kXcds - 1) / kXcds;
+  for (int j = 0; j < kXcds; ++j) {
+    const int q = (xcd + j) % kXcds;
+    const int lo = q * chunk, hi = min(total, lo + chunk);
+    if (lo >= hi) continue;
+    if (atomicAdd(&heads[q], 0) >= hi - lo) continue;  // empty: no increment
+    const int v = atomicAdd(&heads[q], 1);
+    if (lo + v < hi) return lo + v;
+  }
+  return -1;
+}
+
+template <typename S, int NC, bool PULL>
+__global__ void __launch_bounds__(kFusedThreads) k_fused_persistent(Batch Bt, int rbuf, int parts) {
+  __shared__ int item_s;
+  __shared__ Params P_s;
+  __shared__ Buffers D_s;
+  const int total = Bt.off[Bt.nsims] * parts;
+  const int xcd = blockIdx.x % kXcds;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = take_item(Bt.heads, xcd, total);
+    __syncthreads();
+    const int gi = item_s;
+    if (gi < 0) break;  // uniform: every queue is empty
+    const int sim = batch_sim(Bt, gi / parts);
+    stage_struct(P_s, Bt.P[sim]);
+    stage_struct(D_s, Bt.D[sim]);
+    __syncthreads();
+    fused_block<S, NC, PULL>(P_s, D_s, rbuf, gi / parts - Bt.off[sim], gi % parts, parts);
+    __syncthreads();  // the next item overwrites item_s, P_s, D_s and the block's LDS
+  }
 }
 
 // ------------------------------------------------------- in-place step
@@ -2273,11 +2323,27 @@ __global__ void k_batch_offsets(Batch B) {
 __global__ void k_batch_tick(Batch B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < B.nsims) B.D[i].ctrl[kStepCount] += 1;
+  if (i < kXcds) B.heads[i] = 0;  // the persistent step kernel's queues, for the next step
+}
+
+// Resident workgroups of the persistent step kernel on the current device.
+template <typename S, int NC, bool PULL>
+int persistent_grid() {
+  static const int grid = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_persistent<S, NC, PULL>, kFusedThreads, 0) !=
+        hipSuccess)
+      return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+  }();
+  return grid;
 }
 template <typename S, int NC>
 struct BatchL {
   static hipError_t launch(const Params& P0, const Batch& B, int rbuf, bool first, bool progressive,
-                           bool in_place, int parts, hipStream_t st) {
+                           bool in_place, int parts, bool persistent, hipStream_t st) {
     const dim3 gc(grid_for(B.total_capacity)), bc(kThreads), gf(grid_for(B.total_capacity * parts)),
         bf(kFusedThreads);
     if (in_place) {
@@ -2318,10 +2384,21 @@ struct BatchL {
                          (int)kInitNatural, -1);
       hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(64), 0, st, B);
     }
-    if (first)
+    if (persistent) {
+      // resident grid, no more workgroups than items
+      const int items = grid_for(B.total_capacity * parts);
+      const int res = first ? persistent_grid<S, NC, false>() : persistent_grid<S, NC, true>();
+      if (res <= 0) return hipErrorInvalidValue;
+      const dim3 gp(res < items ? res : items);
+      if (first)
+        hipLaunchKernelGGL((k_fused_persistent<S, NC, false>), gp, bf, 0, st, B, rbuf, parts);
+      else
+        hipLaunchKernelGGL((k_fused_persistent<S, NC, true>), gp, bf, 0, st, B, rbuf, parts);
+    } else if (first) {
       hipLaunchKernelGGL((k_fused<S, NC, false, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B, parts);
-    else
+    } else {
       hipLaunchKernelGGL((k_fused<S, NC, true, true>), gf, bf, 0, st, P0, Buffers{}, rbuf, B, parts);
+    }
     hipLaunchKernelGGL(k_batch_tick, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B);
     return hipGetLastError();
   }
@@ -2423,9 +2500,9 @@ hipError_t launch_batch_offsets(const Batch& B, const Params& P0, hipStream_t st
 }
 
 hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool first, bool progressive,
-                             bool in_place, int parts, hipStream_t stream) {
+                             bool in_place, int parts, bool persistent, hipStream_t stream) {
   if (parts != 1 && parts != 2 && parts != 4) return hipErrorInvalidValue;
-  return dispatch<BatchL>(P0, B, rbuf, first, progressive, in_place, parts, stream);
+  return dispatch<BatchL>(P0, B, rbuf, first, progressive, in_place, parts, persistent, stream);
 }
 
 hipError_t launch_candidates(const Params& P, const Buffers& D, hipStream_t stream) {

@@ -79,3 +79,36 @@ def test_split_rejects_bad_values(lbm):
         with pytest.raises(lbm.LbmError):
             lbm.lbm_set_split(sim.h, planes, target)
     sim.close()
+
+
+@pytest.mark.parametrize("planes", [16, 8])
+def test_persistent_batch_gives_the_same_bits(lbm, planes):
+    """The persistent, work-taking schedule of the batched step kernel: every
+    member equal to stepping it alone, graph and eager, static and
+    progressive members, uneven shapes, switching schedules between calls."""
+    from paper_1510_03560_amd import batch
+    shapes = [(48, 32, 32), (40, 24, 56), (64, 32, 48), (33, 47, 26), (96, 32, 32)]
+    for progressive in (True, False):
+        cases = [W.porous_injection(0, seed=50 + k, shape=s, steps=50, progressive=progressive)
+                 for k, s in enumerate(shapes)]
+        alone = []
+        for c in cases:
+            sim = lbm.Simulation(c)
+            sim.step(50)
+            alone.append(snapshot(sim))
+            sim.close()
+        for use_graph in (True, False):
+            sims = [lbm.Simulation(c) for c in cases]
+            lbm.lbm_set_split(sims[0].h, planes, 1024)
+            b = batch.Batch(sims)
+            b.schedule(True)
+            b.step(21, use_graph=use_graph)
+            b.schedule(False)
+            b.step(4, use_graph=use_graph)
+            b.schedule(True)
+            b.step(25, use_graph=use_graph)
+            for s, a in zip(sims, alone):
+                same(snapshot(s), a)
+            b.close()
+            for s in sims:
+                s.close()
