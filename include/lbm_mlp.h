@@ -61,9 +61,11 @@ int lbm_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t t
  * cap are written) or a negative error.  Synchronous. */
 int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap);
 
-/* Enables (enable = 1) or disables the proposal inside lbm_step: after the
- * criterion, every candidate block whose predicted probability exceeds
- * threshold is activated as well.  params: host array of LBM_MLP_NPARAMS
+/* Enables (enable >= 1) or disables (enable <= 0) the proposal inside
+ * lbm_step: after the criterion of every step whose index is a multiple of
+ * enable, every candidate block whose predicted probability exceeds
+ * threshold is activated as well (enable = 1: every step; the network looks
+ * K = 20 steps ahead, so running it every few steps loses little).  params: host array of LBM_MLP_NPARAMS
  * values, copied.  Features of candidate N: the means, over the cells of its
  * active neighbours within shell_width cells of N, of rho_1, rho_2, |u_1|,
  * |u_2|, |psi_1 - psi_rest,1|, |psi_2 - psi_rest,2| (Eq 4-7 on the state the

@@ -54,6 +54,7 @@ struct lbm_handle {
   float* mlp_dev = nullptr;       // proposal network parameters (LBM_MLP_NPARAMS)
   float prop_thr = 0.5f;
   bool prop_enabled = false;
+  int prop_every = 1;             // the proposal runs on steps whose index is a multiple of this
   // once every block holding fluid is active the criterion has no candidates
   // left: the step then skips it (and activation), exactly
   bool mesh_complete = false;
@@ -703,7 +704,7 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
                                      : (kCritRecord | kCritEval | kCritExposure | kCritEmission);
       rc = timed(h, 0, [&] { return launch_criterion(P, h->D, rb, rd, flags, h->stream); });
       if (rc) return rc;
-      if (h->prop_enabled) {
+      if (h->prop_enabled && h->step % h->prop_every == 0) {
         // the learned proposal requests more blocks, ahead of the criterion
         rc = timed(h, 4, [&] {
           hipError_t e = launch_candidates(P, h->D, h->stream);
@@ -991,7 +992,7 @@ int lbm_proposal_features(lbm_t* h, float* feat, int32_t* block, int32_t cap) {
 
 int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t enable) {
   if (!h) return LBM_EINVAL;
-  if (!enable) {
+  if (enable <= 0) {
     h->prop_enabled = false;
     return LBM_OK;
   }
@@ -1003,6 +1004,7 @@ int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t ena
   }
   HIP_TRY(h, hipMemcpy(h->mlp_dev, params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice));
   h->prop_thr = threshold;
+  h->prop_every = enable;
   h->prop_enabled = true;
   return LBM_OK;
 }

@@ -79,26 +79,34 @@ def proposal_features(sim, cap: int = 1 << 16):
     return feat[:n].cpu().numpy().astype(np.float64), blk[:n].cpu().numpy()
 
 
-def set_proposal(sim, params: np.ndarray | None, threshold: float = 0.5):
-    """Enable the proposal in lbm_step (params None disables it)."""
+def set_proposal(sim, params: np.ndarray | None, threshold: float = 0.5, every: int = 1):
+    """Enable the proposal in lbm_step on every `every`-th step (params None
+    disables it)."""
     if params is None:
         _ok(_lib().lbm_set_proposal(sim.h, None, 0.0, 0), sim.h)
         return
     arr = np.ascontiguousarray(params, dtype=np.float32)
-    assert arr.size == NPARAMS
-    _ok(_lib().lbm_set_proposal(sim.h, arr.ctypes.data_as(C.POINTER(C.c_float)), float(threshold), 1), sim.h)
+    assert arr.size == NPARAMS and every >= 1
+    _ok(_lib().lbm_set_proposal(sim.h, arr.ctypes.data_as(C.POINTER(C.c_float)), float(threshold), int(every)),
+        sim.h)
 
 
 def collect(case, steps: int, every: int = 1, K: int = 20, store: int = L.STORE_F32):
     """Runs the criterion-only progressive mesh on `case` and returns
-    (features [m, 12], labels [m], snapshot steps [m], block ids [m])."""
+    (features [m, 12], labels [m], snapshot steps [m], block ids [m]).
+    Snapshots are taken every `every` steps while candidates remain; once
+    the mesh holds every block with fluid there are none, and the run stops
+    (at most `steps` steps)."""
     sim = L.Simulation(case, store=store)
+    n_fluid = sim.stats()["n_fluid_blocks"]
     snaps = []
     for t in range(steps):
         if t % every == 0:
             f, b = proposal_features(sim)
             if len(b):
                 snaps.append((t, f, b))
+            elif t > 0 and sim.stats()["n_active"] >= n_fluid:
+                break
         sim.step(1)
     trace = sim.trace()
     sim.close()
