@@ -691,6 +691,17 @@ def run_porous(args):
     if prog["stats"]["numeric_error"]:
         print("bench: numeric error in the progressive run", file=sys.stderr)
     sim_p.close()
+    # the growth phase of the timed steps, kernel by kernel (a separate run
+    # with HIP events around every launch, which the timed run does without)
+    sim_g, grow = timed_run(True, K, Wm, per_kernel=True)
+    sim_g.close()
+    growth = {
+        "steps": [Wm, Wm + K],
+        "ms_per_step_with_events": round(grow["ms"] / K, 4),
+        "us_per_step": {k: round(v[1] / K * 1e3, 2) for k, v in grow["times"].items() if v[0]},
+        "launches": {k: v[0] for k, v in grow["times"].items() if v[0]},
+    }
+
     sim_s, stat = timed_run(False, K, Wm)
     print(f"bench: static {K} steps {stat['ms']:.1f} ms", file=sys.stderr, flush=True)
 
@@ -707,17 +718,6 @@ def run_porous(args):
     cells_full = stat["stats"]["n_active"] * 4096
     k2_bytes = fused_bytes(fluid_full, cells_full, args.store, pattern, lbm)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
-
-    # the growth phase of the timed steps, kernel by kernel (a separate run
-    # with HIP events around every launch, which the timed run does without)
-    sim_g, grow = timed_run(True, K, Wm, per_kernel=True)
-    sim_g.close()
-    growth = {
-        "steps": [Wm, Wm + K],
-        "ms_per_step_with_events": round(grow["ms"] / K, 4),
-        "us_per_step": {k: round(v[1] / K * 1e3, 2) for k, v in grow["times"].items() if v[0]},
-        "launches": {k: v[0] for k, v in grow["times"].items() if v[0]},
-    }
 
     # time to solution: the whole progressive run against the static mesh
     # (the two give the same bits, hence the same density error)
