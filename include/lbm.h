@@ -91,8 +91,10 @@ typedef struct lbm_params {
   int32_t store;         /* LBM_STORE_* */
   int32_t progressive;   /* 0: static mesh (every block holding fluid active); 1: progressive */
   int32_t pool_blocks;   /* block slots to reserve; 0 = number of blocks holding fluid.  At most
-                            131071 with LBM_STORE_F32 and 262143 with LBM_STORE_F16DEV (the kernels
-                            address a pair of population planes with 32-bit byte offsets) */
+                            65535 with LBM_STORE_F32 and 131071 with LBM_STORE_F16DEV for two
+                            components, 131071 and 262143 for one (the kernels address a pair of
+                            population planes, every component of each link side by side, with
+                            32-bit byte offsets) */
   int32_t pattern;       /* LBM_PATTERN_* */
   double tau[2];         /* > 0.5 */
   double eos_a, eos_b, eos_R, eos_omega, T_over_Tc;

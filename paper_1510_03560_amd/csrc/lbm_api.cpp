@@ -173,13 +173,16 @@ double w_host(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 
 int padded(int n) { return (n + kB - 1) / kB * kB; }
 
 // Largest pool the kernels can address.  They form 32-bit byte offsets within
-// the two planes of an opposite-direction pair (2 * plane * sizeof(population))
-// and within one mask, density or psi plane (4 * plane), with plane =
-// (slots + 1) * 4096 cells: the pool must keep both below 2^32.
-int max_slots(int store) {
+// the two planes of an opposite-direction pair, which hold every component of
+// each link (2 * plane * ncomp * sizeof(population)), and within one mask,
+// density or psi plane (4 * plane), with plane = (slots + 1) * 4096 cells: the
+// pool must keep both below 2^32.
+int max_slots(int store, int ncomp) {
   const uint64_t lim = (uint64_t)1 << 32;
   const uint64_t fsz = store == LBM_STORE_F16DEV ? 2 : 4;
-  const uint64_t per_slot = (uint64_t)kCells * (2 * fsz > 4 ? 2 * fsz : 4);
+  const uint64_t nc = ncomp == 2 ? 2 : 1;
+  const uint64_t pair = 2 * fsz * nc;
+  const uint64_t per_slot = (uint64_t)kCells * (pair > 4 ? pair : 4);
   return (int)(lim / per_slot) - 1;
 }
 
@@ -285,10 +288,10 @@ int validate(const lbm_params* p) {
   if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
   if (p->store == LBM_STORE_F32 || p->store == LBM_STORE_F16DEV) {
-    const int lim = max_slots(p->store);
+    const int lim = max_slots(p->store, p->ncomp);
     if (p->pool_blocks > lim)
       return fail(nullptr, LBM_EINVAL, "pool_blocks %d exceeds the %d block slots the kernels can address with this "
-                  "store", p->pool_blocks, lim);
+                  "store and component count", p->pool_blocks, lim);
   }
   if (p->pattern != LBM_PATTERN_AB && p->pattern != LBM_PATTERN_AA)
     return fail(nullptr, LBM_EINVAL, "pattern must be LBM_PATTERN_AB or LBM_PATTERN_AA");
@@ -512,9 +515,9 @@ int lbm_plan_bytes(const lbm_params* p, const uint8_t* solid, int64_t* bytes) {
   for (uint8_t v : bfluid) n_fluid += v;
   const int nb = (int)bfluid.size();
   const int cap = pool_capacity(*p, n_fluid, nb);
-  if (cap > max_slots(p->store))
+  if (cap > max_slots(p->store, p->ncomp))
     return fail(nullptr, LBM_EINVAL, "%d block slots needed, but the kernels address at most %d with this store", cap,
-                max_slots(p->store));
+                max_slots(p->store, p->ncomp));
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   *bytes = kCreateBytes + geometry_layout(*p, cap, nb, N).total(*p);
   return LBM_OK;
@@ -531,11 +534,11 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   h->n_fluid_blocks = 0;
   for (int b = 0; b < P.nb; ++b) h->n_fluid_blocks += h->bfluid_h[b];
   const int cap = pool_capacity(h->user, h->n_fluid_blocks, P.nb);
-  if (cap > max_slots(h->user.store))
+  if (cap > max_slots(h->user.store, h->user.ncomp))
     return fail(h, LBM_EINVAL,
                 "%d block slots needed, but the kernels address at most %d with this store (32-bit offsets "
                 "within a pair of population planes); use the FP16-deviation store or a smaller lattice",
-                cap, max_slots(h->user.store));
+                cap, max_slots(h->user.store, h->user.ncomp));
   P.capacity = cap;
   P.plane = (uint32_t)((int64_t)(cap + 1) * kCells);
   const GeometryLayout L = geometry_layout(h->user, cap, P.nb, N);

@@ -121,6 +121,69 @@ __device__ __forceinline__ void st_stream(__half* base, uint32_t off, __half v) 
                               reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(base) + off));
 }
 
+// ------------------------------------------------------ population layout
+// Plane i of a population buffer holds direction i of every cell of every
+// slot, with the components of a cell side by side: component a of cell c
+// (slot * 4096 + in-block index) is element (i * plane + c) * ncomp + a.  A
+// link's values for every component then travel in one load and one store,
+// which halves the memory instructions of the two-component step (the step
+// kernels are bound by how many they issue, not by the bytes).  Opposite
+// directions are adjacent planes (2p - 1, 2p): a pull reaches either plane
+// of a pair from the pair's base with a 32-bit byte offset, and the host
+// keeps 2 * plane * ncomp * sizeof(value) within 2^32.
+__host__ __device__ __forceinline__ size_t pop_index(int i, uint32_t c, int a, int ncomp, uint32_t plane) {
+  return ((size_t)i * plane + c) * (size_t)ncomp + (size_t)a;
+}
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// The NC stored values of one link, loaded with one instruction at byte
+// offset off from base.
+template <typename T, int NC>
+__device__ __forceinline__ void ld_link(const T* base, uint32_t off, T (&v)[NC]) {
+  static_assert(NC == 1 || NC == 2, "one or two components");
+  if constexpr (NC == 1) {
+    v[0] = ld(base, off);
+  } else if constexpr (std::is_same<T, float>::value) {
+    const float2v w = ld(reinterpret_cast<const float2v*>(base), off);
+    v[0] = w.x;
+    v[1] = w.y;
+  } else {
+    const uint32_t w = ld(reinterpret_cast<const uint32_t*>(base), off);
+    v[0] = __ushort_as_half((unsigned short)(w & 0xFFFFu));
+    v[1] = __ushort_as_half((unsigned short)(w >> 16));
+  }
+}
+
+// Stores the NC values of one link with one instruction; STREAM: with the
+// non-temporal hint.
+template <bool STREAM, typename T, int NC>
+__device__ __forceinline__ void st_link(T* base, uint32_t off, const T (&v)[NC]) {
+  static_assert(NC == 1 || NC == 2, "one or two components");
+  if constexpr (NC == 1) {
+    if constexpr (STREAM)
+      st_stream(base, off, v[0]);
+    else
+      st(base, off, v[0]);
+  } else if constexpr (std::is_same<T, float>::value) {
+    float2v w;
+    w.x = v[0];
+    w.y = v[1];
+    float2v* p = reinterpret_cast<float2v*>(reinterpret_cast<char*>(base) + off);
+    if constexpr (STREAM)
+      __builtin_nontemporal_store(w, p);
+    else
+      *p = w;
+  } else {
+    const uint32_t w = (uint32_t)__half_as_ushort(v[0]) | ((uint32_t)__half_as_ushort(v[1]) << 16);
+    uint32_t* p = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + off);
+    if constexpr (STREAM)
+      __builtin_nontemporal_store(w, p);
+    else
+      *p = w;
+  }
+}
+
 // --------------------------------------------------------- storage codecs
 struct StoreF32 {
   using T = float;
@@ -440,35 +503,43 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
   }
 }
 
-// As gather, with the reference density of direction i given by ref(I).
-template <typename S, typename Ref>
-__device__ __forceinline__ void gather_ref(const typename S::T* __restrict__ fb, uint32_t plane, int a,
-                                           const Sources<S::kRef>& s, Ref&& ref, float f[kQ]) {
+// Populations of every component arriving at the cell (decoded to FP32),
+// one load per link.  ref(a, I): the FP16 store's reference density of
+// component a for direction I (not called with the FP32 store).
+template <typename S, int NC, typename Ref>
+__device__ __forceinline__ void gather_links(const typename S::T* __restrict__ fb, uint32_t plane,
+                                             const Sources<S::kRef>& s, Ref&& ref, float f[NC][kQ]) {
   using T = typename S::T;
-  constexpr uint32_t sz = sizeof(T);
-  const T* base0 = fb + (size_t)(a * kQ) * plane;
+  constexpr uint32_t stride = NC * sizeof(T);
   unroll<kQ>([&](auto K) {
     constexpr int i = decltype(K)::value;
-    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-    const T v = ld(base0 + (size_t)first * plane, s.fidx[i] * sz);
-    f[i] = S::decode(v, dir_w(i) * ref(K));
+    constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);  // first plane of the pair
+    T v[NC];
+    ld_link<T, NC>(fb + (size_t)first * plane * NC, s.fidx[i] * stride, v);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      if constexpr (S::kRef)
+        f[a][i] = S::decode(v[a], dir_w(i) * ref(a, K));
+      else
+        f[a][i] = S::decode(v[a], 0.0f);
+    }
   });
 }
 
-// Populations of component a arriving at the cell (decoded to FP32).
-//   fb: buffer base; plane: elements per plane; rref: densities of the
-//   previous step (FP16 store only).
-template <typename S>
+// Populations of component a (of NC) arriving at the cell (decoded to FP32).
+//   fb: buffer base; plane: cells per plane; rref: densities of the previous
+//   step (FP16 store only).
+template <typename S, int NC>
 __device__ __forceinline__ void gather(const typename S::T* __restrict__ fb, uint32_t plane, int a,
                                        const Sources<S::kRef>& s, const float* __restrict__ rref, float f[kQ]) {
   using T = typename S::T;
-  constexpr uint32_t sz = sizeof(T);
-  const T* base0 = fb + (size_t)(a * kQ) * plane;
+  constexpr uint32_t stride = NC * sizeof(T);
+  const T* base0 = fb + a;  // component a of every link
   const float* rbase = S::kRef ? rref + (size_t)a * plane : nullptr;
   unroll<kQ>([&](auto K) {
     constexpr int i = decltype(K)::value;
     constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);  // first plane of the pair
-    const T v = ld(base0 + (size_t)first * plane, s.fidx[i] * sz);
+    const T v = ld(base0 + (size_t)first * plane * NC, s.fidx[i] * stride);
     float wr = 0.0f;
     if constexpr (S::kRef) wr = dir_w(i) * ld(rbase, s.ridx[i] * 4u);
     f[i] = S::decode(v, wr);
@@ -793,11 +864,11 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
                                     : S::encode(fe[i], dir_w(i) * rref);
           if (stash[i] != ~0u) {
             // moved here; the sender's address reads as the rest state again
-            typename S::T* sp = fb + (size_t)(a * kQ + dir_opp(i)) * plane + stash[i];
+            typename S::T* sp = fb + pop_index(dir_opp(i), stash[i], a, ncomp, plane);
             v = *sp;
             *sp = stored_rest(a, dir_opp(i));
           }
-          fb[(size_t)(a * kQ + i) * plane + cid] = v;
+          fb[pop_index(i, cid, a, ncomp, plane)] = v;
         });
         if constexpr (S::kRef) {
           D.rho[0][(size_t)a * plane + cid] = rref;
@@ -842,7 +913,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
-      gather<S>(fb, plane, a, src, rref, f);
+      gather<S, NC>(fb, plane, a, src, rref, f);
       float psi = P.psi_rest[a];
       if (kind == kFluid) {
         bool cl;
@@ -1033,7 +1104,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
-      gather<S>(fb, plane, a, src, rref, f);
+      gather<S, NC>(fb, plane, a, src, rref, f);
       const Vec3 Fa = kind == kFluid ? add_body(P, a, F[a], moments(f).rho) : F[a];
       dbg_psi[a * N + n] = psi_c[a];
       dbg_force[(a * 3 + 0) * N + n] = Fa.x;
@@ -1200,25 +1271,19 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
           Sources<S::kRef> src;
           pull_axes_z(z, pa);
           sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cell, m, plane, ctx.nslot, P.capacity, src);
+          // FP16 store: references from the LDS ring, the source cell's, or
+          // the cell's own for a bounced link (and on the first step, which
+          // does not stream)
+          gather_links<S, NC>(fb, plane, src,
+                              [&](int a, auto I) {
+                                constexpr int i = decltype(I)::value;
+                                const bool self = !PULL || i == 0 || ((m >> i) & 1u);
+                                return self ? rref_s[z & 3][a][rcol]
+                                            : rref_s[(z - dir_ez(i)) & 3][a][rcol - dir_ex(i) - kRW * dir_ey(i)];
+                              },
+                              f);
 #pragma unroll
-          for (int a = 0; a < NC; ++a) {
-            if constexpr (S::kRef) {
-              // references from the LDS ring: the source cell, or the cell
-              // itself for a bounced link (and on the first step, which does
-              // not stream)
-              gather_ref<S>(fb, plane, a, src,
-                            [&](auto I) {
-                              constexpr int i = decltype(I)::value;
-                              const bool self = !PULL || i == 0 || ((m >> i) & 1u);
-                              return self ? rref_s[z & 3][a][rcol]
-                                          : rref_s[(z - dir_ez(i)) & 3][a][rcol - dir_ex(i) - kRW * dir_ey(i)];
-                            },
-                            f[a]);
-            } else {
-              gather<S>(fb, plane, a, src, rref, f[a]);
-            }
-            rho[a] = moments(f[a]).rho;
-          }
+          for (int a = 0; a < NC; ++a) rho[a] = moments(f[a]).rho;
         }
         if (kind == kFluid) {
 #pragma unroll
@@ -1284,17 +1349,19 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
       }
       // one store per population for the whole wave, fluid and boundary
       // lanes alike, so that each written line is complete in one request
+      if constexpr (S::kRef) {
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
-        unroll<kQ>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-          constexpr bool second = i != 0 && !(i & 1);
-          const typename S::T enc = S::encode(fp[a][i], dir_w(i) * rr[a]);
-          st_stream(fw + (size_t)(a * kQ + first) * plane, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
-        });
+        for (int a = 0; a < NC; ++a) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
       }
+      unroll<kQ>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        constexpr bool second = i != 0 && !(i & 1);
+        typename S::T enc[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) enc[a] = S::encode(fp[a][i], dir_w(i) * rr[a]);
+        st_link<true>(fw + (size_t)first * plane * NC, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
+      });
     }
     // ---- keep plane z for its store at the next iteration
     store_next = own;
@@ -1475,11 +1542,13 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv,
       Sources<S::kRef> src;
       pull_axes_z(z, pa);
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      float f[NC][kQ];
+      gather_links<S, NC>(fb, plane, src,
+                          [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
+                          f);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
-        const float rho = moments(f).rho;
+        const float rho = moments(f[a]).rho;
         bool cl;
         psi[a] = pseudo_potential(P, a, rho, cl);
         clamps += cl ? 1u : 0u;
@@ -1574,24 +1643,18 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
     if (kind == kFluid || (S::kRef && kind != kSolid)) {
       Sources<S::kRef> src;
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      // FP16 store: the source cell's reference, or the cell's own for a
+      // bounced link (and on the first step, which reads in place)
+      gather_links<S, NC>(fb, plane, src,
+                          [&](int a, auto I) {
+                            constexpr int i = decltype(I)::value;
+                            const bool self = RD == kRdOwn || i == 0 || ((m >> i) & 1u);
+                            return self ? rref_s[z & 3][a][hp]
+                                        : rref_s[(z - dir_ez(i)) & 3][a][hp - dir_ex(i) - kH * dir_ey(i)];
+                          },
+                          fp);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        if constexpr (S::kRef) {
-          // the source cell's reference, or the cell's own for a bounced
-          // link (and on the first step, which reads in place)
-          gather_ref<S>(fb, plane, a, src,
-                        [&](auto I) {
-                          constexpr int i = decltype(I)::value;
-                          const bool self = RD == kRdOwn || i == 0 || ((m >> i) & 1u);
-                          return self ? rref_s[z & 3][a][hp]
-                                      : rref_s[(z - dir_ez(i)) & 3][a][hp - dir_ex(i) - kH * dir_ey(i)];
-                        },
-                        fp[a]);
-        } else {
-          gather<S>(fb, plane, a, src, rref, fp[a]);
-        }
-        rr[a] = moments(fp[a]).rho;
-      }
+      for (int a = 0; a < NC; ++a) rr[a] = moments(fp[a]).rho;
     }
     if (kind == kFluid) {
       float psi_c[NC];
@@ -1639,19 +1702,18 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
     // even index: every line is written whole by one store of the wave,
     // non-temporal; odd index: the shifted stores write parts of lines that
     // other waves complete, which the L2 merges while it holds them
+    if constexpr (S::kRef) {
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      if constexpr (S::kRef) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
-      unroll<kQ>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
-        const T enc = S::encode(fp[a][i], dir_w(i) * rr[a]);
-        if constexpr (kOdd)
-          st(fb + (size_t)(a * kQ + first) * plane, dst[i] * (uint32_t)sizeof(T), enc);
-        else
-          st_stream(fb + (size_t)(a * kQ + first) * plane, dst[i] * (uint32_t)sizeof(T), enc);
-      });
+      for (int a = 0; a < NC; ++a) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
     }
+    unroll<kQ>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+      T enc[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) enc[a] = S::encode(fp[a][i], dir_w(i) * rr[a]);
+      st_link<!kOdd>(fb + (size_t)first * plane * NC, dst[i] * (uint32_t)sizeof(enc), enc);
+    });
   }
 }
 
@@ -1773,24 +1835,27 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
-#pragma unroll
-      for (int a = 0; a < NC; ++a) gather<S>(fb, plane, a, src, rref, f[a]);
+      gather_links<S, NC>(fb, plane, src,
+                          [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
+                          f);
     }
     uint32_t bad = 0u;  // failing links
     if ((flags & kCritEmission) && out_links) {
       uint32_t em[NC][kQ];
+      unroll<kQ - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        constexpr int first = (i & 1) ? i : i - 1;
+        // f*_i(x) is stored at (x, plane i), or with the in-place pattern
+        // at (x, opposite plane) after either parity of step
+        constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
+        typename S::T v[NC];
+        ld_link<typename S::T, NC>(fb + (size_t)first * plane * NC, (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(v), v);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        unroll<kQ - 1>([&](auto I) {
-          constexpr int i = decltype(I)::value + 1;
-          constexpr int first = (i & 1) ? i : i - 1;
-          // f*_i(x) is stored at (x, plane i), or with the in-place pattern
-          // at (x, opposite plane) after either parity of step
-          constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
-          em[a][i] = S::bits(ld(fb + (size_t)(a * kQ + first) * plane,
-                                (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(typename S::T)));
-        });
-        if constexpr (S::kRef) em[a][0] = __float_as_uint(ld(rref + (size_t)a * plane, cid * 4u));
+        for (int a = 0; a < NC; ++a) em[a][i] = S::bits(v[a]);
+      });
+      if constexpr (S::kRef) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) em[a][0] = __float_as_uint(ld(rref + (size_t)a * plane, cid * 4u));
       }
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
@@ -1984,7 +2049,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
+        gather<S, NC>(fb, plane, a, src, rref, f);
         const Mom mo = moments(f);
         float inv = 0.0f;
         if (mo.rho > 0.0f) inv = 1.0f / mo.rho;
@@ -2125,7 +2190,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
       Mom mo = {0.0f, 0.0f, 0.0f, 0.0f};
       if (!sol) {
         float f[kQ];
-        gather<S>(fb, plane, a, src, rref, f);
+        gather<S, NC>(fb, plane, a, src, rref, f);
         mo = moments(f);
       }
       float inv = 0.0f;
@@ -2185,7 +2250,7 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
-      gather<S>(fb, plane, a, src, rref, f);
+      gather<S, NC>(fb, plane, a, src, rref, f);
       acc[a] += (double)moments(f).rho;
     }
   }

@@ -134,22 +134,27 @@ def test_null_handle_calls(L):
 
 
 def test_pool_beyond_32bit_offsets_rejected(L):
-    """The kernels address a pair of population planes with 32-bit byte
-    offsets: a pool of more than 131071 slots (FP32 store) or 262143 (FP16
-    store) is refused before anything is allocated."""
-    for store, lim in ((L.STORE_F32, 131071), (L.STORE_F16DEV, 262143)):
-        p = L.make_params(W.droplet_periodic(32, 0).params, store=store, pool_blocks=lim + 1)
+    """The kernels address a pair of population planes, which hold every
+    component of each link side by side, with 32-bit byte offsets: a pool of
+    more than 2^32 / (4096 * 2 * ncomp * value bytes) - 1 slots is refused
+    before anything is allocated."""
+    two = W.droplet_periodic(32, 0).params
+    one = dict(two, ncomp=1)
+    for params, store, lim in ((two, L.STORE_F32, 65535), (two, L.STORE_F16DEV, 131071),
+                               (one, L.STORE_F32, 131071), (one, L.STORE_F16DEV, 262143)):
+        p = L.make_params(params, store=store, pool_blocks=lim + 1)
         with pytest.raises(L.LbmError) as ei:
             L.lbm_create(p, stream=0)
         assert ei.value.code == -1 and "pool_blocks" in str(ei.value)
         p.pool_blocks = lim
         assert L.lbm_plan_bytes(p) > 0  # at the limit: accepted (pool clamped to the 8 blocks)
-    # a lattice whose fluid blocks alone exceed the FP32 limit: 1024 x 1024 x 512
-    # cells, no solid, 131072 blocks (planned on the host only, never allocated)
-    q = dict(W.porous_injection(64, 0).params, nx=1024, ny=1024, nz=512)
+    # a two-component lattice whose fluid blocks alone exceed the FP32 limit:
+    # 1024 x 512 x 512 cells, no solid, 65536 blocks (planned on the host only,
+    # never allocated); the FP16 store addresses them
+    q = dict(W.porous_injection(64, 0).params, nx=1024, ny=512, nz=512)
     with pytest.raises(L.LbmError) as ei:
         L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F32))
-    assert "131071" in str(ei.value)
+    assert "65535" in str(ei.value)
     assert L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F16DEV)) > 0
 
 
