@@ -53,7 +53,7 @@ int main(void) {
   p.nx = 40;
   EXPECT(lbm_create(&p, NULL, NULL, &h) == LBM_EINVAL);
   p = base(48, 32, 32);
-  p.pool_blocks = 131072;
+  p.pool_blocks = 65536; /* beyond the two-component FP32 limit; within the FP16 one */
   EXPECT(lbm_create(&p, NULL, NULL, &h) == LBM_EINVAL);
   p.store = LBM_STORE_F16DEV;
   EXPECT(lbm_plan_bytes(&p, NULL, &bytes) == LBM_OK && bytes > 0);
