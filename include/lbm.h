@@ -108,7 +108,10 @@ typedef struct lbm_params {
 } lbm_params;
 
 /* Device allocator used for every device buffer of a handle.  alloc returns
- * NULL on failure; free accepts what alloc returned.  ctx is passed through. */
+ * NULL on failure, else memory aligned to 256 bytes (as hipMalloc's is; the
+ * kernels make 16-byte accesses from the start of a buffer, and a misaligned
+ * block is released and reported as LBM_EINVAL); free accepts what alloc
+ * returned.  ctx is passed through. */
 typedef struct lbm_allocator {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
@@ -129,6 +132,10 @@ typedef struct lbm_stats {
   int32_t numeric_error;    /* nonzero once a density was non-positive or non-finite */
   int32_t pool_full;        /* nonzero if an activation did not fit the pool */
   int64_t activations;      /* blocks activated so far, by lbm_activate or the criterion (trace entries) */
+  int32_t repacked;         /* progressive mesh: nonzero once every block holding fluid was active and
+                               lbm_step put the slots in block order (the static mesh's layout, which
+                               its steps then run as fast as); the fields are unchanged by it */
+  int32_t reserved;
 } lbm_stats_t;
 /* leak: number of (step, cell, direction) links in which an active cell
  * showed a non-solid cell of an inactive block a pseudo-potential other than

@@ -58,6 +58,10 @@ struct lbm_handle {
   // once every block holding fluid is active the criterion has no candidates
   // left: the step then skips it (and activation), exactly
   bool mesh_complete = false;
+  // once complete, the slots are put in block order (the static mesh's
+  // layout) by one pass over the slot-indexed arrays
+  bool repacked = false;
+  bool misaligned = false;          // the caller's allocator returned memory not aligned to 256 bytes
   int32_t* nact_pinned = nullptr;  // pinned host copy of n_active
   hipEvent_t nact_ev = nullptr;
   bool nact_pending = false;
@@ -106,6 +110,12 @@ void* dev_alloc(lbm_t* h, size_t bytes) {
   if (bytes == 0) bytes = 4;
   if (h->custom_alloc) {
     p = h->alloc.alloc(bytes, h->alloc.ctx);
+    // the kernels use 16-byte accesses from the start of each buffer
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255u)) {
+      h->alloc.free(p, h->alloc.ctx);
+      p = nullptr;
+      h->misaligned = true;
+    }
   } else if (hipMalloc(&p, bytes) != hipSuccess) {
     p = nullptr;
   }
@@ -452,8 +462,10 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   h->D.ctrl = (int32_t*)dev_alloc(h, sizeof(int32_t) * kNumCtrl);
   h->D.counters = (unsigned long long*)dev_alloc(h, sizeof(unsigned long long) * 4);
   if (!h->scratch_f || !h->scratch_i || !h->mass_dev || !h->D.ctrl || !h->D.counters) {
+    const bool misaligned = h->misaligned;
     dev_free_all(h);
     delete h;
+    if (misaligned) return fail(nullptr, LBM_EINVAL, "the allocator returned memory not aligned to 256 bytes");
     return fail(nullptr, LBM_ENOMEM, "device allocation failed");
   }
   float bg[2] = {(float)p->bg_rho[0], (float)(p->ncomp == 2 ? p->bg_rho[1] : p->bg_rho[0])};
@@ -566,8 +578,10 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   if (!D.f[0] || !D.f[1] || (aa && !D.psi) || (f16 && (!D.rho[0] || !D.rho[1])) || !D.mask ||
       (h->user.progressive && !D.uprev) || !D.block_slot ||
       !D.slot_block || !D.order || !D.frontier || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
-      !D.cand || !D.trace)
+      !D.cand || !D.trace) {
+    if (h->misaligned) return fail(h, LBM_EINVAL, "the allocator returned memory not aligned to 256 bytes");
     return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
+  }
   h->slot_bytes = L.slot_bytes;
   // initial fields, FP32; NaN marks a component of a cell at the rest state
   if (rho0 || u0) {
@@ -699,6 +713,12 @@ int lbm_step(lbm_t* h, int32_t nsteps) {
       h->nact_pending = false;
       if (*h->nact_pinned > h->n_est) h->n_est = *h->nact_pinned;
       if (*h->nact_pinned >= h->n_fluid_blocks) h->mesh_complete = true;
+      if (h->mesh_complete && !h->repacked) {
+        // slots in block order from here on: the layout of the static mesh
+        const hipError_t e = launch_repack(P, h->D, rb, aa, h->stream);
+        if (e != hipSuccess) return fail(h, LBM_EHIP, "repack: %s", hipGetErrorString(e));
+        h->repacked = true;
+      }
     }
     if (h->user.progressive && !h->mesh_complete) {
       // criterion and leak checks on the frontier, then the requested blocks
@@ -886,6 +906,8 @@ int lbm_stats(lbm_t* h, lbm_stats_t* out) {
   out->numeric_error = ctrl[kNumeric];
   out->pool_full = ctrl[kPoolFull];
   out->activations = ctrl[kTraceLen];
+  out->repacked = h->repacked ? 1 : 0;
+  out->reserved = 0;
   if (h->geometry) {
     double m[4] = {0, 0, 0, 0};
     HIP_TRY(h, hipMemsetAsync(h->mass_dev, 0, sizeof m, h->stream));

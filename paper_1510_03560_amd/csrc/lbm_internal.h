@@ -172,6 +172,11 @@ hipError_t launch_batch_step(const Batch& B, const Params& P0, int rbuf, bool fi
                              bool in_place, int parts, bool persistent, hipStream_t stream);
 hipError_t launch_export(const Params& P, const Buffers& D, int rbuf, int rd, float* rho, float* u,
                          float* umix, hipStream_t stream);
+// Puts the slots in block order (slot j takes the block of D.order[j]) once
+// every block holding fluid is active: every slot-indexed plane is permuted
+// through the buffer the next step writes (two buffers) or the psi planes
+// (in place); rbuf: the population buffer the next step reads.
+hipError_t launch_repack(const Params& P, const Buffers& D, int rbuf, bool in_place, hipStream_t stream);
 // out[n] = 1 for cells of active blocks (lattice-wide, N bytes).
 hipError_t launch_active_cells(const Params& P, const Buffers& D, uint8_t* out, hipStream_t stream);
 // Staging for lbm_moments_noalloc: a fixed device array of

@@ -2179,6 +2179,49 @@ __global__ void k_active_cells(Params P, Buffers D, uint8_t* out) {
   }
 }
 
+// ---------------------------------------------------------------- repack
+// Once every block holding fluid is active, the slots are put in block order:
+// slot j takes the block of D.order[j], the j-th active slot in block order.
+// The progressive mesh then lays its blocks out as the static mesh does
+// (neighbours along x in adjacent slots), and its steps run as fast.  Each
+// slot-indexed plane is gathered into a scratch region and copied back, one
+// plane at a time; the slot tables follow last.  Only slots below n_active
+// move (the rest slot stays where it is).
+//   slot_vec: 16-byte words per slot in the plane; gather: read slot order[j]
+//   (else slot j) into slot j.
+__global__ void k_repack_plane(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                               const int32_t* __restrict__ order, const int32_t* __restrict__ ctrl,
+                               uint32_t slot_vec, int gather) {
+  const long long total = (long long)ctrl[kNActive] * slot_vec;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / slot_vec);
+    const uint32_t w = (uint32_t)(e % slot_vec);
+    const int from = gather ? order[j] : j;
+    dst[(size_t)j * slot_vec + w] = src[(size_t)from * slot_vec + w];
+  }
+}
+
+// Slot tables: tmp[j] = block of slot order[j], tmp[cap + j] = its frontier flag.
+__global__ void k_repack_tables_gather(Buffers D, int32_t* tmp, int cap) {
+  const int n = D.ctrl[kNActive];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int from = D.order[j];
+    tmp[j] = D.slot_block[from];
+    tmp[cap + j] = D.frontier[from];
+  }
+}
+__global__ void k_repack_tables_apply(Buffers D, const int32_t* tmp, int cap) {
+  const int n = D.ctrl[kNActive];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int b = tmp[j];
+    D.slot_block[j] = b;
+    D.frontier[j] = tmp[cap + j];
+    D.block_slot[b] = j;
+    D.order[j] = j;
+  }
+}
+
 // Moments (Eq 4-5) of the active blocks into lattice-wide arrays.
 template <typename S, int NC, int RD>
 __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rbuf, float* rho, float* u,
@@ -2553,6 +2596,43 @@ hipError_t static_staging(float** out) {
 
 hipError_t launch_active_cells(const Params& P, const Buffers& D, uint8_t* out, hipStream_t stream) {
   hipLaunchKernelGGL(k_active_cells, dim3(2048), dim3(256), 0, stream, P, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_repack(const Params& P, const Buffers& D, int rbuf, bool in_place, hipStream_t stream) {
+  // scratch: the population buffer the next step writes (two buffers), or
+  // the psi planes, which the next step computes again (in place); either
+  // holds at least one plane of any slot-indexed array
+  char* scratch = reinterpret_cast<char*>(in_place ? static_cast<void*>(D.psi) : D.f[rbuf ^ 1]);
+  if (!scratch) return hipErrorInvalidValue;
+  const size_t plane = P.plane;
+  const dim3 grid(1024), block(256);
+  hipError_t e = hipSuccess;
+  auto one = [&](void* base, size_t bytes_per_cell) {
+    if (e != hipSuccess) return;
+    const uint32_t slot_vec = (uint32_t)(kCells * bytes_per_cell / 16);
+    hipLaunchKernelGGL(k_repack_plane, grid, block, 0, stream, reinterpret_cast<const uint4*>(base),
+                       reinterpret_cast<uint4*>(scratch), D.order, D.ctrl, slot_vec, 1);
+    hipLaunchKernelGGL(k_repack_plane, grid, block, 0, stream, reinterpret_cast<const uint4*>(scratch),
+                       reinterpret_cast<uint4*>(base), D.order, D.ctrl, slot_vec, 0);
+    e = hipGetLastError();
+  };
+  // the populations the next step reads: one plane per direction, every
+  // component of a link side by side
+  const size_t link = (size_t)P.ncomp * (P.store ? 2 : 4);
+  char* f = reinterpret_cast<char*>(D.f[rbuf]);
+  for (int i = 0; i < kQ; ++i) one(f + (size_t)i * plane * link, link);
+  one(D.mask, 4);
+  if (D.uprev)
+    for (int k = 0; k < 3 * P.ncomp; ++k) one(D.uprev + (size_t)k * plane, 4);
+  if (P.store)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < P.ncomp; ++a) one(D.rho[b] + (size_t)a * plane, 4);
+  if (e != hipSuccess) return e;
+  int32_t* tmp = reinterpret_cast<int32_t*>(scratch);
+  hipLaunchKernelGGL(k_repack_tables_gather, dim3(256), block, 0, stream, D, tmp, P.capacity);
+  hipLaunchKernelGGL(k_repack_tables_apply, dim3(256), block, 0, stream, D, static_cast<const int32_t*>(tmp),
+                     P.capacity);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ class lbm_stats_t(C.Structure):
         ("capacity", C.c_int32), ("store", C.c_int32), ("bytes_reserved", C.c_int64),
         ("bytes_active", C.c_int64), ("mass", C.c_double * 2), ("leak", C.c_int64), ("clamps", C.c_int64),
         ("numeric_error", C.c_int32), ("pool_full", C.c_int32), ("activations", C.c_int64),
+        ("repacked", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

@@ -27,6 +27,7 @@ hipError_t launch_export(const Params&, const Buffers&, int, int, float*, float*
   return hipErrorNoDevice;
 }
 hipError_t launch_active_cells(const Params&, const Buffers&, uint8_t*, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_repack(const Params&, const Buffers&, int, bool, hipStream_t) { return hipErrorNoDevice; }
 hipError_t static_staging(float** out) {
   *out = nullptr;
   return hipErrorNoDevice;

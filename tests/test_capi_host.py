@@ -173,6 +173,23 @@ def test_refusing_allocator_gives_enomem(L):
     assert len(calls) >= 1
 
 
+def test_misaligned_allocator_refused(L):
+    """Memory from the caller's allocator must be aligned to 256 bytes (the
+    kernels make 16-byte accesses from a buffer's start): a misaligned block
+    is released at once and lbm_create fails with LBM_EINVAL, before any
+    device call."""
+    freed = []
+    alloc_t = dict(L.lbm_allocator._fields_)["alloc"]
+    free_t = dict(L.lbm_allocator._fields_)["free"]
+    a = L.lbm_allocator(alloc_t(lambda n, ctx: 0x10000 + 8), free_t(lambda p, ctx: freed.append(p)), None)
+    p = L.make_params(W.droplet_periodic(32, 0).params)
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_create(p, stream=0, allocator=a)
+    assert ei.value.code == -1
+    assert "aligned to 256" in str(ei.value)
+    assert freed and all(f == 0x10000 + 8 for f in freed)
+
+
 def test_padded_lattice_plan(L):
     """Non-periodic axes of any length are padded to whole 16^3 blocks; a
     periodic axis must be a multiple of 16."""
