@@ -94,7 +94,9 @@ typedef struct lbm_params {
                             65535 with LBM_STORE_F32 and 131071 with LBM_STORE_F16DEV for two
                             components, 131071 and 262143 for one (the kernels address a pair of
                             population planes, every component of each link side by side, with
-                            32-bit byte offsets) */
+                            32-bit byte offsets); when the padded nx is a multiple of 256 (16
+                            blocks) the slots are padded to 4160 cells and the limits are 64526,
+                            129054, 129054 and 258110 */
   int32_t pattern;       /* LBM_PATTERN_* */
   double tau[2];         /* > 0.5 */
   double eos_a, eos_b, eos_R, eos_omega, T_over_Tc;

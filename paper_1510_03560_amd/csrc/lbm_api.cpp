@@ -182,17 +182,27 @@ double w_host(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 
 // reading of uneven edges: walls).
 int padded(int n) { return (n + kB - 1) / kB * kB; }
 
+// Cells a slot spans in every plane.  With a multiple of 16 blocks along x,
+// the neighbours of a block along y sit 16 * k slots away, a power-of-two
+// multiple of the slot's bytes, and the step kernel ran 7 % slower on such
+// meshes (256^3: 1.75 against 1.63 ms); 64 cells of padding per slot (1.6 %
+// more memory) remove that.  Other meshes run 1 % faster unpadded.
+uint32_t slot_cells_for(const lbm_params& u) {
+  const int nbx = padded(u.nx) / kB;
+  return nbx % 16 == 0 ? (uint32_t)kCells + 64u : (uint32_t)kCells;
+}
+
 // Largest pool the kernels can address.  They form 32-bit byte offsets within
 // the two planes of an opposite-direction pair, which hold every component of
 // each link (2 * plane * ncomp * sizeof(population)), and within one mask,
-// density or psi plane (4 * plane), with plane = (slots + 1) * 4096 cells: the
+// density or psi plane (4 * plane), with plane = (slots + 1) * slot_cells: the
 // pool must keep both below 2^32.
-int max_slots(int store, int ncomp) {
+int max_slots(const lbm_params& u) {
   const uint64_t lim = (uint64_t)1 << 32;
-  const uint64_t fsz = store == LBM_STORE_F16DEV ? 2 : 4;
-  const uint64_t nc = ncomp == 2 ? 2 : 1;
+  const uint64_t fsz = u.store == LBM_STORE_F16DEV ? 2 : 4;
+  const uint64_t nc = u.ncomp == 2 ? 2 : 1;
   const uint64_t pair = 2 * fsz * nc;
-  const uint64_t per_slot = (uint64_t)kCells * (pair > 4 ? pair : 4);
+  const uint64_t per_slot = (uint64_t)slot_cells_for(u) * (pair > 4 ? pair : 4);
   return (int)(lim / per_slot) - 1;
 }
 
@@ -211,7 +221,7 @@ struct GeometryLayout {
 size_t at_least_4(size_t b) { return b == 0 ? 4 : b; }
 
 GeometryLayout geometry_layout(const lbm_params& u, int cap, int nb, int64_t N) {
-  const size_t plane = (size_t)(cap + 1) * kCells;
+  const size_t plane = (size_t)(cap + 1) * slot_cells_for(u);
   const size_t fsz = u.store == LBM_STORE_F16DEV ? 2 : 4;
   const bool f16 = u.store == LBM_STORE_F16DEV, aa = u.pattern == LBM_PATTERN_AA;
   GeometryLayout L;
@@ -227,7 +237,7 @@ GeometryLayout geometry_layout(const lbm_params& u, int cap, int nb, int64_t N) 
   L.trace = at_least_4(sizeof(int32_t) * 2 * (size_t)kTraceCap);
   L.init_rho = at_least_4(sizeof(float) * u.ncomp * (size_t)N);
   L.init_u = at_least_4(sizeof(float) * 3 * (size_t)N);
-  L.slot_bytes = (int64_t)kCells * ((int64_t)(aa ? 1 : 2) * fsz * u.ncomp * kQ + (f16 ? 8 * u.ncomp : 0) +
+  L.slot_bytes = (int64_t)slot_cells_for(u) * ((int64_t)(aa ? 1 : 2) * fsz * u.ncomp * kQ + (f16 ? 8 * u.ncomp : 0) +
                                     (aa ? 4 * u.ncomp : 0) + 4 + (u.progressive ? 12 * u.ncomp : 0));
   return L;
 }
@@ -298,7 +308,7 @@ int validate(const lbm_params* p) {
   if (p->progressive != 0 && p->progressive != 1) return fail(nullptr, LBM_EINVAL, "progressive must be 0 or 1");
   if (p->pool_blocks < 0) return fail(nullptr, LBM_EINVAL, "pool_blocks must be >= 0");
   if (p->store == LBM_STORE_F32 || p->store == LBM_STORE_F16DEV) {
-    const int lim = max_slots(p->store, p->ncomp);
+    const int lim = max_slots(*p);
     if (p->pool_blocks > lim)
       return fail(nullptr, LBM_EINVAL, "pool_blocks %d exceeds the %d block slots the kernels can address with this "
                   "store and component count", p->pool_blocks, lim);
@@ -424,6 +434,7 @@ int lbm_create(const lbm_params* p, void* stream, const lbm_allocator* alloc, lb
   P.ny = p->ny;
   P.nz = p->nz;
   P.nbx = padded(p->nx) / kB;
+  P.slot_cells = slot_cells_for(*p);
   P.nby = padded(p->ny) / kB;
   P.nbz = padded(p->nz) / kB;
   P.nb = P.nbx * P.nby * P.nbz;
@@ -527,9 +538,9 @@ int lbm_plan_bytes(const lbm_params* p, const uint8_t* solid, int64_t* bytes) {
   for (uint8_t v : bfluid) n_fluid += v;
   const int nb = (int)bfluid.size();
   const int cap = pool_capacity(*p, n_fluid, nb);
-  if (cap > max_slots(p->store, p->ncomp))
+  if (cap > max_slots(*p))
     return fail(nullptr, LBM_EINVAL, "%d block slots needed, but the kernels address at most %d with this store", cap,
-                max_slots(p->store, p->ncomp));
+                max_slots(*p));
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   *bytes = kCreateBytes + geometry_layout(*p, cap, nb, N).total(*p);
   return LBM_OK;
@@ -546,13 +557,14 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
   h->n_fluid_blocks = 0;
   for (int b = 0; b < P.nb; ++b) h->n_fluid_blocks += h->bfluid_h[b];
   const int cap = pool_capacity(h->user, h->n_fluid_blocks, P.nb);
-  if (cap > max_slots(h->user.store, h->user.ncomp))
+  if (cap > max_slots(h->user))
     return fail(h, LBM_EINVAL,
                 "%d block slots needed, but the kernels address at most %d with this store (32-bit offsets "
                 "within a pair of population planes); use the FP16-deviation store or a smaller lattice",
-                cap, max_slots(h->user.store, h->user.ncomp));
+                cap, max_slots(h->user));
   P.capacity = cap;
-  P.plane = (uint32_t)((int64_t)(cap + 1) * kCells);
+  P.slot_cells = slot_cells_for(h->user);
+  P.plane = (uint32_t)((int64_t)(cap + 1) * P.slot_cells);
   const GeometryLayout L = geometry_layout(h->user, cap, P.nb, N);
   const bool f16 = h->user.store == LBM_STORE_F16DEV;
   const bool aa = in_place(h);

@@ -64,7 +64,8 @@ struct Params {
   int shell;
   int bc[6];
   int capacity;      // usable slots; slot index `capacity` is the rest slot
-  uint32_t plane;    // elements per population plane: (capacity + 1) * 4096
+  uint32_t plane;    // cells per plane: (capacity + 1) * slot_cells
+  uint32_t slot_cells;  // cells a slot spans in every plane: 4096, or 4160 (padded; see the kernels' header)
   int store;         // 0: FP32 populations, 1: FP16 deviations
   int trace_cap;
   int s_zero;        // criterion threshold is exactly zero
@@ -85,7 +86,7 @@ struct Params {
 };
 
 // Device buffers of one handle.
-// A "plane" holds one value per cell of every slot: index slot*4096 + cell.
+// A "plane" holds one value per cell of every slot: index slot*slot_cells + cell.
 struct Buffers {
   void* f[2];             // populations: [ncomp*19 planes] of float or __half (in place: f[1] == f[0],
                           // and the buffer index only selects the reference densities)

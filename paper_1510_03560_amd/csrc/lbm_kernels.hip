@@ -4,16 +4,18 @@
 //
 // Data layout.  The lattice is cut into 16^3 blocks; an active block owns a
 // slot of the pool.  Populations are structure-of-arrays (section 3) by
-// (component, direction) plane over the whole pool:
-//     f[buf][plane = comp*19 + dir][slot*4096 + cell],
+// direction plane over the whole pool, the components of a cell side by side:
+//     f[buf][dir][slot * slot_cells + cell][comp],
 //     cell = (x mod 8) + 8 (y mod 4) + 32 (x div 8) + 64 (y div 4) + 256 z
 // (8 x 4 tiles of x and y, see cell_of), so the 64 lanes of a wave read or
-// write two whole tiles of one plane: 256 contiguous bytes (FP32), two cache
-// lines.  Every pull is a 32-bit element index
-// from a wave-uniform base (the first plane of the opposite-direction pair),
-// which keeps address arithmetic in single VGPRs and lets both components
-// share it.  The extra slot `capacity` holds the rest state and stands in for
-// every inactive block and for the outside of the domain.
+// write two whole tiles of one plane.  slot_cells is 4096, or 4160 when the
+// block grid has a multiple of 16 blocks along x (the host's choice: the
+// padding keeps y and z neighbours from sitting a power-of-two number of
+// bytes apart, which made such meshes 7 % slower).  Every pull is a 32-bit
+// byte offset from a wave-uniform base (the first plane of the
+// opposite-direction pair), which keeps address arithmetic in single VGPRs.
+// The extra slot `capacity` holds the rest state and stands in for every
+// inactive block and for the outside of the domain.
 //
 // One time step (section 4.3) runs
 //   k_criterion : frontier blocks only: pull the shell cells, Eq 13 ->
@@ -124,7 +126,7 @@ __device__ __forceinline__ void st_stream(__half* base, uint32_t off, __half v) 
 // ------------------------------------------------------ population layout
 // Plane i of a population buffer holds direction i of every cell of every
 // slot, with the components of a cell side by side: component a of cell c
-// (slot * 4096 + in-block index) is element (i * plane + c) * ncomp + a.  A
+// (slot * slot_cells + in-block index) is element (i * plane + c) * ncomp + a.  A
 // link's values for every component then travel in one load and one store,
 // which halves the memory instructions of the two-component step (the step
 // kernels are bound by how many they issue, not by the bytes).  Opposite
@@ -450,7 +452,7 @@ __host__ __device__ __forceinline__ void pull_axes_z(int z, PullAxes& a) {
 
 template <int RD, bool REF>
 __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t own, uint32_t m, uint32_t plane,
-                                        const int* nslot, int rest, Sources<REF>& s) {
+                                        const int* nslot, int rest, uint32_t slot_cells, Sources<REF>& s) {
   s.fidx[0] = own;
   if constexpr (REF) s.ridx[0] = own;
   const uint32_t own_second = own + plane;
@@ -476,7 +478,7 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
     unroll<kQ - 1>([&](auto K) {
       constexpr int i = decltype(K)::value + 1;
       constexpr bool second = !(i & 1);  // plane i is the second of its pair
-      const uint32_t src_cell = ((uint32_t)slot[i] << 12) | (w[i] & 0xFFFFu);
+      const uint32_t src_cell = (uint32_t)slot[i] * slot_cells + (w[i] & 0xFFFFu);
       const bool bounce = (m >> i) & 1u;
       const uint32_t own_i = second ? own_second : own;   // (x, plane i)
       const uint32_t own_o = second ? own : own_second;   // (x, plane of the opposite direction)
@@ -774,7 +776,7 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
          c += (int)blockDim.x) {
       int x, y, z;
       cell_xyz(c, x, y, z);
-      const uint32_t cid = (uint32_t)slot * kCells + c;
+      const uint32_t cid = (uint32_t)slot * P.slot_cells + c;
       uint32_t m = 0u;
       long long n = -1;
       const int X = bx * kB + x, Y = by * kB + y, Z = bz * kB + z;
@@ -833,7 +835,7 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
             const int nbk = sx / kB + P.nbx * (sy / kB + P.nby * (sz / kB));
             const int sl = D.block_slot[nbk];
             if (sl >= 0 && D.act_step[nbk] != born)
-              stash[i] = (uint32_t)sl * kCells + cell_of(sx & 15, sy & 15, sz & 15);
+              stash[i] = (uint32_t)sl * P.slot_cells + cell_of(sx & 15, sy & 15, sz & 15);
           }
         });
       }
@@ -900,7 +902,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
     const uint32_t cid = own_base + cell_of(x, y, z);
@@ -909,7 +911,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_psi(Params P, Buffers D, int
     if (kind == kSolid) continue;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
@@ -1061,7 +1063,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
     const int hx = h % kH - 1, hy = (h / kH) % kH - 1, hz = h / (kH * kH) - 1;
     const int d = 13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(hz);
     const int slot = ctx.nslot[d];
-    const uint32_t cid = (uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, hz & 15);
+    const uint32_t cid = (uint32_t)slot * P.slot_cells + cell_of(hx & 15, hy & 15, hz & 15);
 #pragma unroll
     for (int a = 0; a < NC; ++a)
       psi_s[a * kHalo + h] = slot == P.capacity ? P.psi_rest[a] : ld(psi_slots + (size_t)a * plane, cid * 4u);
@@ -1073,7 +1075,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
   pull_axes_xy(x, y, pa);
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
   const long long N = (long long)P.nx * P.ny * P.nz;
 #pragma unroll 1
@@ -1099,7 +1101,7 @@ __global__ void __launch_bounds__(kThreads) k_debug_force(Params P, Buffers D, i
                              F);
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
     const long long n = (bx * kB + x) + (long long)P.nx * ((by * kB + y) + (long long)P.ny * (bz * kB + z));
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
@@ -1189,7 +1191,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
   typename S::T* __restrict__ fw = fplane<S>(D, rbuf ^ 1);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;   // references of f(t)
   float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;     // this step's densities
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   float fp[NC][kQ];   // populations of this column's cell one plane back
   float rp[NC];       // and its densities
   uint32_t mp = 0u;   // and its mask
@@ -1204,7 +1206,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
   // is pending on one path and not on another.
   auto mask_load = [&](int z) -> uint32_t {
     const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
-    return ld(D.mask, ((uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15)) * 4u);
+    return ld(D.mask, ((uint32_t)slot * P.slot_cells + cxy + 256u * (uint32_t)(z & 15)) * 4u);
   };
   // (threads without a column hand over a mask too, which they never read:
   // the select then needs no branch, and the load is consumed on every path)
@@ -1225,7 +1227,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
         const int aa = e / (kRW * kRW), col = e % (kRW * kRW);
         const int rx = col % kRW - 2, ry = col / kRW - 2;
         const int slot = ctx.nslot[13 + sgn_out(rx) + 3 * sgn_out(ry) + 9 * sgn_out(zp)];
-        v[j] = ld(rref + (size_t)aa * plane, ((uint32_t)slot * kCells + cell_of(rx & 15, ry & 15, zp & 15)) * 4u);
+        v[j] = ld(rref + (size_t)aa * plane, ((uint32_t)slot * P.slot_cells + cell_of(rx & 15, ry & 15, zp & 15)) * 4u);
       }
     }
   };
@@ -1259,7 +1261,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
     if (col) {
       float psi[NC];
       const int slot = ctx.nslot[dxy + 9 * sgn_out(z)];
-      const uint32_t cell = (uint32_t)slot * kCells + cxy + 256u * (uint32_t)(z & 15);
+      const uint32_t cell = (uint32_t)slot * P.slot_cells + cxy + 256u * (uint32_t)(z & 15);
 #pragma unroll
       for (int a = 0; a < NC; ++a) psi[a] = P.psi_rest[a];
       if (slot != P.capacity) {
@@ -1270,7 +1272,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
         if (pull) {
           Sources<S::kRef> src;
           pull_axes_z(z, pa);
-          sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cell, m, plane, ctx.nslot, P.capacity, src);
+          sources<PULL ? kRdPull : kRdOwn, S::kRef>(pa, cell, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
           // FP16 store: references from the LDS ring, the source cell's, or
           // the cell's own for a bounced link (and on the first step, which
           // does not stream)
@@ -1555,7 +1557,7 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv,
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, 0);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // references of f(t)
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   unsigned numeric = 0u, clamps = 0u;
 #pragma unroll 1
   for (int z = z0; z < kB; z += kZStep) {
@@ -1568,7 +1570,7 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv,
     if (kind == kFluid) {
       Sources<S::kRef> src;
       pull_axes_z(z, pa);
-      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
       float f[NC][kQ];
       gather_links<S, NC>(fb, plane, src,
                           [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
@@ -1630,7 +1632,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;  // references of f(t)
   float* __restrict__ rnew = S::kRef ? D.rho[rbuf ^ 1] : nullptr;    // this step's densities
   const float* __restrict__ psi_g = D.psi;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   // FP16 store: the references of f(t) over the same footprint (a link's
   // value decodes with its source cell's), in a ring of their own
   __shared__ float rref_s[S::kRef ? kPsiRing : 1][NC][S::kRef ? kFoot : 1];
@@ -1642,7 +1644,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
       const int a = e / kFoot, col = e % kFoot;
       const int hx = col % kH - 1, hy = col / kH - 1;
       const int slot = ctx.nslot[13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(zp)];
-      const uint32_t off = ((uint32_t)slot * kCells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u;
+      const uint32_t off = ((uint32_t)slot * P.slot_cells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u;
       psi_s[zp & 3][a][col] = ld(psi_g + (size_t)a * plane, off);
       if constexpr (S::kRef) rref_s[zp & 3][a][col] = ld(rref + (size_t)a * plane, off);
     }
@@ -1669,7 +1671,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
     // reference of what they write
     if (kind == kFluid || (S::kRef && kind != kSolid)) {
       Sources<S::kRef> src;
-      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
       // FP16 store: the source cell's reference, or the cell's own for a
       // bounced link (and on the first step, which reads in place)
       gather_links<S, NC>(fb, plane, src,
@@ -1722,7 +1724,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
         const uint32_t w = pa.ax[1 + dir_ex(i)] + pa.ay[1 + dir_ey(i)] + pa.az[1 + dir_ez(i)];  // x + e_i
         const int tslot = ctx.nslot[w >> 16];
         const bool keep = kind == kSolid || ((m >> dir_opp(i)) & 1u) || tslot == P.capacity;
-        const uint32_t tcell = ((uint32_t)tslot << 12) | (w & 0xFFFFu);
+        const uint32_t tcell = (uint32_t)tslot * P.slot_cells + (w & 0xFFFFu);
         dst[i] = keep ? own_o : (second ? tcell + plane : tcell);
       }
     });
@@ -1821,7 +1823,7 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   const uint32_t plane = P.plane;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   const bool pull_cells = (flags & (kCritRecord | kCritEval | kCritExposure)) != 0;
   unsigned fired = 0u;
 #pragma unroll 1
@@ -1861,7 +1863,7 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
       pull_axes_xy(x, y, pa);
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
-      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
       gather_links<S, NC>(fb, plane, src,
                           [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
                           f);
@@ -2064,7 +2066,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
 #pragma unroll 1
     for (int c = t; c < total; c += kPropThreads) {
       const int x = x0 + c % lx, y = y0 + (c / lx) % ly, z = z0 + c / (lx * ly);
-      const uint32_t cid = (uint32_t)sB * kCells + cell_of(x, y, z);
+      const uint32_t cid = (uint32_t)sB * P.slot_cells + cell_of(x, y, z);
       const uint32_t m = ld(D.mask, cid * 4u);
       const uint32_t kind = (m >> kKindShift) & 3u;
       if (kind == kSolid) continue;
@@ -2072,7 +2074,7 @@ __global__ void __launch_bounds__(kPropThreads) k_propose(Params P, Buffers D, i
       pull_axes_xy(x, y, pa);
       pull_axes_z(z, pa);
       Sources<S::kRef> src;
-      sources<RD, S::kRef>(pa, cid, m, plane, nslotB, P.capacity, src);
+      sources<RD, S::kRef>(pa, cid, m, plane, nslotB, P.capacity, P.slot_cells, src);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         float f[kQ];
@@ -2240,7 +2242,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
   const int bx = blk % P.nbx, by = (blk / P.nbx) % P.nby, bz = blk / (P.nbx * P.nby);
   const long long N = (long long)P.nx * P.ny * P.nz;
   const uint32_t plane = P.plane;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
 #pragma unroll 1
@@ -2254,7 +2256,7 @@ __global__ void __launch_bounds__(kThreads) k_export(Params P, Buffers D, int rb
     float mr = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       Mom mo = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -2303,7 +2305,7 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
   PullAxes pa;
   pull_axes_xy(x, y, pa);
   const uint32_t plane = P.plane;
-  const uint32_t own_base = (uint32_t)s * kCells;
+  const uint32_t own_base = (uint32_t)s * P.slot_cells;
   const typename S::T* __restrict__ fb = fplane<S>(D, rbuf);
   const float* __restrict__ rref = S::kRef ? D.rho[rbuf] : nullptr;
   double acc[kMaxComp] = {0.0, 0.0};
@@ -2316,7 +2318,7 @@ __global__ void __launch_bounds__(kThreads) k_mass(Params P, Buffers D, int rbuf
     ++nf;
     Sources<S::kRef> src;
     pull_axes_z(z, pa);
-    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, src);
+    sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       float f[kQ];
@@ -2610,7 +2612,7 @@ hipError_t launch_repack(const Params& P, const Buffers& D, int rbuf, bool in_pl
   hipError_t e = hipSuccess;
   auto one = [&](void* base, size_t bytes_per_cell) {
     if (e != hipSuccess) return;
-    const uint32_t slot_vec = (uint32_t)(kCells * bytes_per_cell / 16);
+    const uint32_t slot_vec = (uint32_t)(P.slot_cells * bytes_per_cell / 16);
     hipLaunchKernelGGL(k_repack_plane, grid, block, 0, stream, reinterpret_cast<const uint4*>(base),
                        reinterpret_cast<uint4*>(scratch), D.order, D.ctrl, slot_vec, 1);
     hipLaunchKernelGGL(k_repack_plane, grid, block, 0, stream, reinterpret_cast<const uint4*>(scratch),

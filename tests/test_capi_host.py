@@ -149,13 +149,21 @@ def test_pool_beyond_32bit_offsets_rejected(L):
         p.pool_blocks = lim
         assert L.lbm_plan_bytes(p) > 0  # at the limit: accepted (pool clamped to the 8 blocks)
     # a two-component lattice whose fluid blocks alone exceed the FP32 limit:
-    # 1024 x 512 x 512 cells, no solid, 65536 blocks (planned on the host only,
+    # 1040 x 512 x 512 cells, no solid, 66560 blocks (planned on the host only,
     # never allocated); the FP16 store addresses them
-    q = dict(W.porous_injection(64, 0).params, nx=1024, ny=512, nz=512)
+    q = dict(W.porous_injection(64, 0).params, nx=1040, ny=512, nz=512)
     with pytest.raises(L.LbmError) as ei:
         L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F32))
     assert "65535" in str(ei.value)
     assert L.lbm_plan_bytes(L.make_params(q, store=L.STORE_F16DEV)) > 0
+    # a multiple of 16 blocks along x: slots padded to 4160 cells, lower limits
+    pad = dict(two, nx=256)
+    for store, lim in ((L.STORE_F32, 64526), (L.STORE_F16DEV, 129054)):
+        p = L.make_params(pad, store=store, pool_blocks=lim + 1)
+        with pytest.raises(L.LbmError):
+            L.lbm_create(p, stream=0)
+        p.pool_blocks = lim
+        assert L.lbm_plan_bytes(p) > 0
 
 
 def test_refusing_allocator_gives_enomem(L):
