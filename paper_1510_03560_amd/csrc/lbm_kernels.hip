@@ -724,10 +724,12 @@ __global__ void k_rest_state(Params P, const float* bg, float* out, int* iters) 
 // cell kind), populations of buffer `buf` (placed as `mode` says), psi,
 // reference densities and the criterion history.  Slot `capacity` (the rest
 // slot) is initialised the same way with the rest state everywhere and an
-// all-fluid mask.  A workgroup takes a quarter of a slot (1024 cells, four
+// all-fluid mask.  A workgroup takes a sixteenth of a slot (256 cells, one
 // per thread) at a time, so that a handful of new blocks still spreads over
-// many compute units; the stored rest populations come from LDS.
-constexpr int kInitQuarters = 4;
+// many compute units and no thread waits for the loads of a second cell
+// (a quarter, four cells per thread, took 1.7x as long per growth step); the
+// stored rest populations come from LDS.
+constexpr int kInitParts = 16;
 
 template <typename S, bool BATCH>
 __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, int first_h, int count_h, int from_dev,
@@ -764,15 +766,15 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
     else
       return __ushort_as_half((unsigned short)bits);
   };
-  for (int u = blockIdx.x; u < count * kInitQuarters; u += gridDim.x) {
-    const int slot = first + u / kInitQuarters;
-    const int quarter = u % kInitQuarters;
+  for (int u = blockIdx.x; u < count * kInitParts; u += gridDim.x) {
+    const int slot = first + u / kInitParts;
+    const int part = u % kInitParts;
     const bool rest_slot = slot == P.capacity;
     const int blk = rest_slot ? -1 : D.slot_block[slot];
     const int bx = rest_slot ? 0 : blk % P.nbx, by = rest_slot ? 0 : (blk / P.nbx) % P.nby,
               bz = rest_slot ? 0 : blk / (P.nbx * P.nby);
 #pragma unroll 1
-    for (int c = quarter * (kCells / kInitQuarters) + (int)threadIdx.x; c < (quarter + 1) * (kCells / kInitQuarters);
+    for (int c = part * (kCells / kInitParts) + (int)threadIdx.x; c < (part + 1) * (kCells / kInitParts);
          c += (int)blockDim.x) {
       int x, y, z;
       cell_xyz(c, x, y, z);
@@ -1826,6 +1828,11 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   const uint32_t own_base = (uint32_t)s * P.slot_cells;
   const bool pull_cells = (flags & (kCritRecord | kCritEval | kCritExposure)) != 0;
   unsigned fired = 0u;
+  // each cell's mask is loaded one iteration ahead, so that an iteration
+  // waits for one round trip (its pulls), not two (the mask, then the pulls
+  // whose addresses depend on it)
+  uint32_t m_next = 0u;
+  if ((int)threadIdx.x < n_shell) m_next = ld(D.mask, (own_base + (uint32_t)list[threadIdx.x]) * 4u);
 #pragma unroll 1
   for (int j = threadIdx.x; j < n_shell; j += kThreads) {
     const int c = list[j];
@@ -1833,7 +1840,8 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
     cell_xyz(c, x, y, z);
     const unsigned dirs = shell_dirs(x, y, z, P.shell) & cand;
     const uint32_t cid = own_base + (uint32_t)c;
-    const uint32_t m = ld(D.mask, cid * 4u);
+    const uint32_t m = m_next;
+    if (j + kThreads < n_shell) m_next = ld(D.mask, (own_base + (uint32_t)list[j + kThreads]) * 4u);
     const uint32_t kind = (m >> kKindShift) & 3u;
     if (kind == kSolid) continue;
     // the previous velocities, loaded before the pulls so that both are in
@@ -2375,7 +2383,7 @@ template <typename S, int NC>
 struct InitL {
   static hipError_t launch(const Params& P, const Buffers& D, int buf, int first, int count, bool from_dev,
                            bool use_init, int mode, int born, hipStream_t st) {
-    const int grid = from_dev ? 1024 : (count > 0 ? (count * kInitQuarters < 8192 ? count * kInitQuarters : 8192) : 1);
+    const int grid = from_dev ? 2048 : (count > 0 ? (count * kInitParts < 8192 ? count * kInitParts : 8192) : 1);
     hipLaunchKernelGGL((k_init<S, false>), dim3(grid), dim3(256), 0, st, P, D, buf, first, count, from_dev ? 1 : 0,
                        use_init ? 1 : 0, Batch{}, mode, born);
     return hipGetLastError();
