@@ -213,8 +213,21 @@ struct Mom {
   float rho, jx, jy, jz;
 };
 
-__device__ __forceinline__ Mom moments(const float f[kQ]) {
+// Momentum of f, with its density already summed (by moments() on the same
+// values, so the bits are those moments() would give).
+__device__ __forceinline__ Mom moments_with_rho(const float f[kQ], float rho) {
   Mom m;
+  const float d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6];
+  const float d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12];
+  const float d13 = f[13] - f[14], d15 = f[15] - f[16], d17 = f[17] - f[18];
+  m.rho = rho;
+  m.jx = (((d1 + d7) + d9) + d11) + d13;
+  m.jy = (((d3 + d7) - d9) + d15) + d17;
+  m.jz = (((d5 + d11) - d13) + d15) - d17;
+  return m;
+}
+
+__device__ __forceinline__ Mom moments(const float f[kQ]) {
   float r = f[0];
   r = r + (f[1] + f[2]);
   r = r + (f[3] + f[4]);
@@ -225,28 +238,22 @@ __device__ __forceinline__ Mom moments(const float f[kQ]) {
   r = r + (f[13] + f[14]);
   r = r + (f[15] + f[16]);
   r = r + (f[17] + f[18]);
-  const float d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6];
-  const float d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12];
-  const float d13 = f[13] - f[14], d15 = f[15] - f[16], d17 = f[17] - f[18];
-  m.rho = r;
-  m.jx = (((d1 + d7) + d9) + d11) + d13;
-  m.jy = (((d3 + d7) - d9) + d15) + d17;
-  m.jz = (((d5 + d11) - d13) + d15) - d17;
-  return m;
+  return moments_with_rho(f, r);
 }
 
 // ------------------------------------------------------------------- EOS
 // Eq 7 (Peng-Robinson, denominator 1 + 2 b rho - b^2 rho^2) and Eq 6.  A
 // negative radicand gives psi = 0 and is reported through `clamped`.
-// The two terms of Eq 7 are put over their common denominator (one division)
-// and the square root is the hardware one (1 ulp).
+// The two terms of Eq 7 are put over their common denominator, divided by
+// with the hardware reciprocal (1 ulp), and the square root is the hardware
+// one (1 ulp).
 __device__ __forceinline__ float pseudo_potential(const Params& P, int a, float rho, bool& clamped) {
   const float g = P.g_self[a];
   clamped = false;
   if (g == 0.0f) return 0.0f;
   const float brho = P.b * rho;
   const float d1 = 1.0f - brho, d2 = (1.0f + 2.0f * brho) - brho * brho;
-  const float p = ((rho * P.RT) * d2 - (P.a_theta * rho * rho) * d1) / (d1 * d2);
+  const float p = ((rho * P.RT) * d2 - (P.a_theta * rho * rho) * d1) * __builtin_amdgcn_rcpf(d1 * d2);
   const float rad = (p - kThird * rho) * (6.0f / g);  // 2 (p - c_s^2 rho) / (c_s^2 g)
   if (!(rad >= 0.0f)) {
     clamped = true;
@@ -357,12 +364,14 @@ __device__ __forceinline__ void collide_emit(float omega, const float f[kQ], con
     const float eu = edot<ex, ey, ez>(ux, uy, uz);
     const float ed = edot<ex, ey, ez>(dx, dy, dz);
     const float es = edot<ex, ey, ez>(sx, sy, sz);
-    const float even = we + w45 * (eu * eu);
+    // explicit fused multiply-adds: the same rounding in every kernel that
+    // inlines this function (no contraction is left to the compiler)
+    const float even = __builtin_fmaf(w45, eu * eu, we);
     const float odd = w3 * eu;
-    const float deven = wdv + w45 * (ed * es);
+    const float deven = __builtin_fmaf(w45, ed * es, wdv);
     const float dodd = w3 * ed;
-    const float oi = (f[i] + omega * ((even + odd) - f[i])) + (deven + dodd);
-    const float oj = (f[j] + omega * ((even - odd) - f[j])) + (deven - dodd);
+    const float oi = __builtin_fmaf(omega, (even + odd) - f[i], f[i]) + (deven + dodd);
+    const float oj = __builtin_fmaf(omega, (even - odd) - f[j], f[j]) + (deven - dodd);
     emit(std::integral_constant<int, i>{}, oi);
     emit(std::integral_constant<int, j>{}, oj);
     rest = i == 1 ? (oi + oj) : rest + (oi + oj);
@@ -1337,7 +1346,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
         // pair is read before it is written)
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-          const Mom mo = moments(fp[a]);
+          const Mom mo = moments_with_rho(fp[a], rp[a]);  // rp: the density the pull summed
           rr[a] = rp[a];
           collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho),
                        [&](auto I, float v) { fp[a][decltype(I)::value] = v; });
@@ -1701,7 +1710,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
                              F);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        const Mom mo = moments(fp[a]);
+        const Mom mo = moments_with_rho(fp[a], rr[a]);  // rr: the density summed after the pull
         collide_emit(P.omega[a], fp[a], mo, add_body(P, a, F[a], mo.rho),
                      [&](auto I, float v) { fp[a][decltype(I)::value] = v; });
       }
