@@ -123,6 +123,34 @@ __device__ __forceinline__ void st_stream(__half* base, uint32_t off, __half v) 
                               reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(base) + off));
 }
 
+// ------------------------------------------------- reference densities
+// FP16 store: the reference densities of a cell (its density of the step
+// that wrote its populations), the components side by side: element
+// cell * ncomp + a of D.rho[b]; one load or store per cell.
+template <int NC>
+__device__ __forceinline__ void ld_refs(const float* base, uint32_t cell, float (&r)[NC]) {
+  if constexpr (NC == 1) {
+    r[0] = ld(base, cell * 4u);
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 w = ld(reinterpret_cast<const f2*>(base), cell * 8u);
+    r[0] = w.x;
+    r[1] = w.y;
+  }
+}
+template <int NC>
+__device__ __forceinline__ void st_refs(float* base, uint32_t cell, const float (&r)[NC]) {
+  if constexpr (NC == 1) {
+    st(base, cell * 4u, r[0]);
+  } else {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 w;
+    w.x = r[0];
+    w.y = r[1];
+    st(reinterpret_cast<f2*>(base), cell * 8u, w);
+  }
+}
+
 // ------------------------------------------------------ population layout
 // Plane i of a population buffer holds direction i of every cell of every
 // slot, with the components of a cell side by side: component a of cell c
@@ -515,11 +543,12 @@ __host__ __device__ __forceinline__ void sources(const PullAxes& pa, uint32_t ow
 }
 
 // Populations of every component arriving at the cell (decoded to FP32),
-// one load per link.  ref(a, I): the FP16 store's reference density of
-// component a for direction I (not called with the FP32 store).
-template <typename S, int NC, typename Ref>
+// one load per link.  refs(I, r): the FP16 store's reference densities of
+// every component for direction I, into r[NC] (not called with the FP32
+// store).
+template <typename S, int NC, typename Refs>
 __device__ __forceinline__ void gather_links(const typename S::T* __restrict__ fb, uint32_t plane,
-                                             const Sources<S::kRef>& s, Ref&& ref, float f[NC][kQ]) {
+                                             const Sources<S::kRef>& s, Refs&& refs, float f[NC][kQ]) {
   using T = typename S::T;
   constexpr uint32_t stride = NC * sizeof(T);
   unroll<kQ>([&](auto K) {
@@ -527,12 +556,14 @@ __device__ __forceinline__ void gather_links(const typename S::T* __restrict__ f
     constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);  // first plane of the pair
     T v[NC];
     ld_link<T, NC>(fb + (size_t)first * plane * NC, s.fidx[i] * stride, v);
+    if constexpr (S::kRef) {
+      float r[NC];
+      refs(K, r);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      if constexpr (S::kRef)
-        f[a][i] = S::decode(v[a], dir_w(i) * ref(a, K));
-      else
-        f[a][i] = S::decode(v[a], 0.0f);
+      for (int a = 0; a < NC; ++a) f[a][i] = S::decode(v[a], dir_w(i) * r[a]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) f[a][i] = S::decode(v[a], 0.0f);
     }
   });
 }
@@ -546,13 +577,13 @@ __device__ __forceinline__ void gather(const typename S::T* __restrict__ fb, uin
   using T = typename S::T;
   constexpr uint32_t stride = NC * sizeof(T);
   const T* base0 = fb + a;  // component a of every link
-  const float* rbase = S::kRef ? rref + (size_t)a * plane : nullptr;
+  const float* rbase = S::kRef ? rref + a : nullptr;  // component a of each cell's references
   unroll<kQ>([&](auto K) {
     constexpr int i = decltype(K)::value;
     constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);  // first plane of the pair
     const T v = ld(base0 + (size_t)first * plane * NC, s.fidx[i] * stride);
     float wr = 0.0f;
-    if constexpr (S::kRef) wr = dir_w(i) * ld(rbase, s.ridx[i] * 4u);
+    if constexpr (S::kRef) wr = dir_w(i) * ld(rbase, s.ridx[i] * (uint32_t)(4 * NC));
     f[i] = S::decode(v, wr);
   });
 }
@@ -884,8 +915,8 @@ __global__ void __launch_bounds__(256) k_init(Params Pv, Buffers Dv, int buf, in
           fb[pop_index(i, cid, a, ncomp, plane)] = v;
         });
         if constexpr (S::kRef) {
-          D.rho[0][(size_t)a * plane + cid] = rref;
-          D.rho[1][(size_t)a * plane + cid] = rref;
+          D.rho[0][(size_t)cid * ncomp + a] = rref;
+          D.rho[1][(size_t)cid * ncomp + a] = rref;
         }
         if (!rest_slot && D.uprev)
           for (int d = 0; d < 3; ++d) D.uprev[((size_t)(a * 3 + d)) * plane + cid] = 0.0f;
@@ -1227,7 +1258,8 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
     const uint32_t raw = mask_load(z0 - 1);
     mask_s[0][t] = in_mesh(z0 - 1) ? raw : kNoCell;
   }
-  // references of plane zp: entries t, t + 384, ... of the NC x 400 values
+  // references of plane zp: entries t, t + 384, ... of the 400 x NC values
+  // (entry e: column e / NC, component e % NC, as they lie in memory)
   constexpr int kRefPer = (NC * kRW * kRW + kFusedThreads - 1) / kFusedThreads;
   auto rref_fetch = [&](int zp, float (&v)[kRefPer]) {
 #pragma unroll
@@ -1235,10 +1267,11 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
       const int e = t + j * kFusedThreads;
       v[j] = 0.0f;
       if (e < NC * kRW * kRW) {
-        const int aa = e / (kRW * kRW), col = e % (kRW * kRW);
+        const int aa = e % NC, col = e / NC;
         const int rx = col % kRW - 2, ry = col / kRW - 2;
         const int slot = ctx.nslot[13 + sgn_out(rx) + 3 * sgn_out(ry) + 9 * sgn_out(zp)];
-        v[j] = ld(rref + (size_t)aa * plane, ((uint32_t)slot * P.slot_cells + cell_of(rx & 15, ry & 15, zp & 15)) * 4u);
+        const uint32_t cell = (uint32_t)slot * P.slot_cells + cell_of(rx & 15, ry & 15, zp & 15);
+        v[j] = ld(rref, (cell * NC + (uint32_t)aa) * 4u);
       }
     }
   };
@@ -1246,7 +1279,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
 #pragma unroll
     for (int j = 0; j < kRefPer; ++j) {
       const int e = t + j * kFusedThreads;
-      if (e < NC * kRW * kRW) rref_s[ring & 3][e / (kRW * kRW)][e % (kRW * kRW)] = v[j];
+      if (e < NC * kRW * kRW) rref_s[ring & 3][e % NC][e / NC] = v[j];
     }
   };
   const int rcol = (cy + 2) * kRW + (cx + 2);  // this column in the reference footprint
@@ -1288,11 +1321,13 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
           // the cell's own for a bounced link (and on the first step, which
           // does not stream)
           gather_links<S, NC>(fb, plane, src,
-                              [&](int a, auto I) {
+                              [&](auto I, float (&r)[NC]) {
                                 constexpr int i = decltype(I)::value;
                                 const bool self = !PULL || i == 0 || ((m >> i) & 1u);
-                                return self ? rref_s[z & 3][a][rcol]
-                                            : rref_s[(z - dir_ez(i)) & 3][a][rcol - dir_ex(i) - kRW * dir_ey(i)];
+#pragma unroll
+                                for (int a = 0; a < NC; ++a)
+                                  r[a] = self ? rref_s[z & 3][a][rcol]
+                                              : rref_s[(z - dir_ez(i)) & 3][a][rcol - dir_ex(i) - kRW * dir_ey(i)];
                               },
                               f);
 #pragma unroll
@@ -1362,10 +1397,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
       }
       // one store per population for the whole wave, fluid and boundary
       // lanes alike, so that each written line is complete in one request
-      if constexpr (S::kRef) {
-#pragma unroll
-        for (int a = 0; a < NC; ++a) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
-      }
+      if constexpr (S::kRef) st_refs<NC>(rnew, cid, rr);
       unroll<kQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
@@ -1584,8 +1616,7 @@ __global__ void __launch_bounds__(kThreads) k_inplace_psi(Params Pv, Buffers Dv,
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
       float f[NC][kQ];
       gather_links<S, NC>(fb, plane, src,
-                          [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
-                          f);
+                          [&](auto I, float (&r)[NC]) { ld_refs<NC>(rref, src.ridx[decltype(I)::value], r); }, f);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         const float rho = moments(f[a]).rho;
@@ -1657,7 +1688,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
       const int slot = ctx.nslot[13 + sgn_out(hx) + 3 * sgn_out(hy) + 9 * sgn_out(zp)];
       const uint32_t off = ((uint32_t)slot * P.slot_cells + cell_of(hx & 15, hy & 15, zp & 15)) * 4u;
       psi_s[zp & 3][a][col] = ld(psi_g + (size_t)a * plane, off);
-      if constexpr (S::kRef) rref_s[zp & 3][a][col] = ld(rref + (size_t)a * plane, off);
+      if constexpr (S::kRef) rref_s[zp & 3][a][col] = ld(rref, off * NC + (uint32_t)(4 * a));
     }
   };
   psi_load(-1);
@@ -1686,11 +1717,13 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
       // FP16 store: the source cell's reference, or the cell's own for a
       // bounced link (and on the first step, which reads in place)
       gather_links<S, NC>(fb, plane, src,
-                          [&](int a, auto I) {
+                          [&](auto I, float (&r)[NC]) {
                             constexpr int i = decltype(I)::value;
                             const bool self = RD == kRdOwn || i == 0 || ((m >> i) & 1u);
-                            return self ? rref_s[z & 3][a][hp]
-                                        : rref_s[(z - dir_ez(i)) & 3][a][hp - dir_ex(i) - kH * dir_ey(i)];
+#pragma unroll
+                            for (int a = 0; a < NC; ++a)
+                              r[a] = self ? rref_s[z & 3][a][hp]
+                                          : rref_s[(z - dir_ez(i)) & 3][a][hp - dir_ex(i) - kH * dir_ey(i)];
                           },
                           fp);
 #pragma unroll
@@ -1742,10 +1775,7 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
     // even index: every line is written whole by one store of the wave,
     // non-temporal; odd index: the shifted stores write parts of lines that
     // other waves complete, which the L2 merges while it holds them
-    if constexpr (S::kRef) {
-#pragma unroll
-      for (int a = 0; a < NC; ++a) st(rnew + (size_t)a * plane, cid * 4u, rr[a]);
-    }
+    if constexpr (S::kRef) st_refs<NC>(rnew, cid, rr);
     unroll<kQ>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
@@ -1882,8 +1912,7 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
       Sources<S::kRef> src;
       sources<RD, S::kRef>(pa, cid, m, plane, ctx.nslot, P.capacity, P.slot_cells, src);
       gather_links<S, NC>(fb, plane, src,
-                          [&](int a, auto I) { return ld(rref + (size_t)a * plane, src.ridx[decltype(I)::value] * 4u); },
-                          f);
+                          [&](auto I, float (&r)[NC]) { ld_refs<NC>(rref, src.ridx[decltype(I)::value], r); }, f);
     }
     uint32_t bad = 0u;  // failing links
     if ((flags & kCritEmission) && out_links) {
@@ -1900,8 +1929,10 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
         for (int a = 0; a < NC; ++a) em[a][i] = S::bits(v[a]);
       });
       if constexpr (S::kRef) {
+        float r[NC];
+        ld_refs<NC>(rref, cid, r);
 #pragma unroll
-        for (int a = 0; a < NC; ++a) em[a][0] = __float_as_uint(ld(rref + (size_t)a * plane, cid * 4u));
+        for (int a = 0; a < NC; ++a) em[a][0] = __float_as_uint(r[a]);
       }
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
@@ -2645,8 +2676,7 @@ hipError_t launch_repack(const Params& P, const Buffers& D, int rbuf, bool in_pl
   if (D.uprev)
     for (int k = 0; k < 3 * P.ncomp; ++k) one(D.uprev + (size_t)k * plane, 4);
   if (P.store)
-    for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < P.ncomp; ++a) one(D.rho[b] + (size_t)a * plane, 4);
+    for (int b = 0; b < 2; ++b) one(D.rho[b], (size_t)4 * P.ncomp);
   if (e != hipSuccess) return e;
   int32_t* tmp = reinterpret_cast<int32_t*>(scratch);
   hipLaunchKernelGGL(k_repack_tables_gather, dim3(256), block, 0, stream, D, tmp, P.capacity);
