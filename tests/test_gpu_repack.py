@@ -64,3 +64,32 @@ def test_repacked_mesh_keeps_static_bits(L, store, pattern, pool):
         assert np.array_equal(a, b)
     for a, b in zip(end, ref_end):
         assert np.array_equal(a, b)
+
+
+def test_repacked_members_in_a_batch(L):
+    """Members whose slots were repacked by lbm_step, then stepped as a batch
+    (graph replay): the same bits as stepping them alone."""
+    from paper_1510_03560_amd import batch
+    cases = [W.porous_injection(0, seed=s, shape=(48, 32, 32), steps=0) for s in (11, 12)]
+    print("repacked members in a batch", flush=True)
+    sims = [L.Simulation(c) for c in cases]
+    steps = 0
+    while not all(s.stats()["repacked"] for s in sims) and steps < 4000:
+        for s in sims:
+            s.step(32)
+        steps += 32
+    assert all(s.stats()["repacked"] for s in sims)
+    b = batch.Batch(sims)
+    b.step(40, use_graph=True)
+    steps += 40
+    got = [s.moments()[:3] for s in sims]
+    b.close()
+    for s in sims:
+        s.close()
+    for c, g in zip(cases, got):
+        ref = L.Simulation(c)
+        ref.step(steps)
+        want = ref.moments()[:3]
+        ref.close()
+        for a, w in zip(g, want):
+            assert np.array_equal(a, w)
