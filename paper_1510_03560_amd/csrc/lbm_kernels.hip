@@ -229,7 +229,10 @@ struct StoreF16 {
   static constexpr bool kRef = true;
   static constexpr float kScale = 4096.0f;
   static constexpr float kInvScale = 1.0f / 4096.0f;
-  __device__ static __forceinline__ float decode(T v, float wr) { return wr + __half2float(v) * kInvScale; }
+  // wr + h 2^-12 as one fused multiply-add: the product is exact (a power-of-two
+  // scaling of a half value, never below the FP32 normal range), so the one
+  // rounding is that of the addition, the same bits as the separate operations
+  __device__ static __forceinline__ float decode(T v, float wr) { return __builtin_fmaf(__half2float(v), kInvScale, wr); }
   __device__ static __forceinline__ T encode(float f, float wr) { return __float2half_rn((f - wr) * kScale); }
   __device__ static __forceinline__ uint32_t bits(T v) { return (uint32_t)__half_as_ushort(v); }
 };
