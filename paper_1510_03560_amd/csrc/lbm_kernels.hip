@@ -220,6 +220,8 @@ struct StoreF32 {
   static constexpr bool kRef = false;
   __device__ static __forceinline__ float decode(T v, float) { return v; }
   __device__ static __forceinline__ T encode(float f, float) { return f; }
+  static constexpr float kScale = 1.0f;
+  __device__ static __forceinline__ T encode_scaled(float f, float) { return f; }
   __device__ static __forceinline__ uint32_t bits(T v) { return __float_as_uint(v); }
 };
 
@@ -234,6 +236,12 @@ struct StoreF16 {
   // rounding is that of the addition, the same bits as the separate operations
   __device__ static __forceinline__ float decode(T v, float wr) { return __builtin_fmaf(__half2float(v), kInvScale, wr); }
   __device__ static __forceinline__ T encode(float f, float wr) { return __float2half_rn((f - wr) * kScale); }
+  // encode with the reference given already scaled, wrs = wr 2^12 (exact):
+  // f 2^12 - wrs is (f - wr) 2^12 before its one rounding, so the fused form
+  // gives the bits of encode(f, wr)
+  __device__ static __forceinline__ T encode_scaled(float f, float wrs) {
+    return __float2half_rn(__builtin_fmaf(f, kScale, -wrs));
+  }
   __device__ static __forceinline__ uint32_t bits(T v) { return (uint32_t)__half_as_ushort(v); }
 };
 
@@ -1401,13 +1409,16 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
       // one store per population for the whole wave, fluid and boundary
       // lanes alike, so that each written line is complete in one request
       if constexpr (S::kRef) st_refs<NC>(rnew, cid, rr);
+      float rrs[NC];  // the references scaled by the store's 2^12 (exact): w_i rrs = (w_i rr) 2^12
+#pragma unroll
+      for (int a = 0; a < NC; ++a) rrs[a] = rr[a] * S::kScale;
       unroll<kQ>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
         constexpr bool second = i != 0 && !(i & 1);
         typename S::T enc[NC];
 #pragma unroll
-        for (int a = 0; a < NC; ++a) enc[a] = S::encode(fp[a][i], dir_w(i) * rr[a]);
+        for (int a = 0; a < NC; ++a) enc[a] = S::encode_scaled(fp[a][i], dir_w(i) * rrs[a]);
         st_link<true>(fw + (size_t)first * plane * NC, (cid + (second ? plane : 0u)) * (uint32_t)sizeof(enc), enc);
       });
     }
@@ -1779,12 +1790,15 @@ __global__ void __launch_bounds__(kInplaceThreads) k_inplace_collide(Params Pv, 
     // non-temporal; odd index: the shifted stores write parts of lines that
     // other waves complete, which the L2 merges while it holds them
     if constexpr (S::kRef) st_refs<NC>(rnew, cid, rr);
+    float rrs[NC];  // the references scaled by the store's 2^12 (exact): w_i rrs = (w_i rr) 2^12
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rrs[a] = rr[a] * S::kScale;
     unroll<kQ>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int first = i == 0 ? 0 : ((i & 1) ? i : i - 1);
       T enc[NC];
 #pragma unroll
-      for (int a = 0; a < NC; ++a) enc[a] = S::encode(fp[a][i], dir_w(i) * rr[a]);
+      for (int a = 0; a < NC; ++a) enc[a] = S::encode_scaled(fp[a][i], dir_w(i) * rrs[a]);
       st_link<!kOdd>(fb + (size_t)first * plane * NC, dst[i] * (uint32_t)sizeof(enc), enc);
     });
   }
