@@ -126,6 +126,15 @@ void* dev_alloc(lbm_t* h, size_t bytes) {
   return p;
 }
 
+// A device allocation that failed: LBM_EINVAL when the caller's allocator
+// returned memory that is not aligned to 256 bytes (dev_alloc released it),
+// else LBM_ENOMEM.
+int alloc_failed(lbm_t* h, const char* what) {
+  if (h->misaligned)
+    return fail(h, LBM_EINVAL, "the allocator returned memory not aligned to 256 bytes (%s)", what);
+  return fail(h, LBM_ENOMEM, "device allocation failed (%s)", what);
+}
+
 void dev_free_all(lbm_t* h) {
   for (void* p : h->owned) {
     if (h->custom_alloc)
@@ -591,8 +600,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
       (h->user.progressive && !D.uprev) || !D.block_slot ||
       !D.slot_block || !D.order || !D.frontier || !D.bfluid || !D.solid || !D.request || !D.expose || !D.act_step || !D.bfrac ||
       !D.cand || !D.trace) {
-    if (h->misaligned) return fail(h, LBM_EINVAL, "the allocator returned memory not aligned to 256 bytes");
-    return fail(h, LBM_ENOMEM, "device allocation failed (%d block slots)", cap);
+    return alloc_failed(h, "block pool");
   }
   h->slot_bytes = L.slot_bytes;
   // initial fields, FP32; NaN marks a component of a cell at the rest state
@@ -608,12 +616,12 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, const double* rho0, const d
     if (u0)
       for (int64_t k = 0; k < 3 * N; ++k) u[k] = (float)u0[k];
     h->init_rho = (float*)dev_alloc(h, L.init_rho);
-    if (!h->init_rho) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
+    if (!h->init_rho) return alloc_failed(h, "initial fields");
     HIP_TRY(h, hipMemcpy(h->init_rho, r.data(), sizeof(float) * r.size(), hipMemcpyHostToDevice));
     D.init_rho = h->init_rho;
     if (u0) {
       h->init_u = (float*)dev_alloc(h, L.init_u);
-      if (!h->init_u) return fail(h, LBM_ENOMEM, "device allocation failed (initial fields)");
+      if (!h->init_u) return alloc_failed(h, "initial fields");
       HIP_TRY(h, hipMemcpy(h->init_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice));
       D.init_u = h->init_u;
     }
@@ -807,7 +815,7 @@ int lbm_moments(lbm_t* h, double* rho, double* u, double* umix, uint8_t* active)
     if (d_r) dev_free_one(h, d_r, sizeof(float) * nr);
     if (d_u) dev_free_one(h, d_u, sizeof(float) * nu);
     if (d_m) dev_free_one(h, d_m, sizeof(float) * nm);
-    return fail(h, LBM_ENOMEM, "device allocation failed (moments)");
+    return alloc_failed(h, "moments");
   }
   rc = lbm_moments_device(h, d_r, d_u, d_m);
   std::vector<float> tmp;
@@ -963,7 +971,7 @@ int lbm_debug_fields(lbm_t* h, int which, double* out) {
     if (d_p) dev_free_one(h, d_p, sizeof(float) * np);
     if (d_f) dev_free_one(h, d_f, sizeof(float) * nf);
     if (d_s) dev_free_one(h, d_s, sizeof(float) * ns);
-    return fail(h, LBM_ENOMEM, "device allocation failed (debug)");
+    return alloc_failed(h, "debug");
   }
   hipError_t e = hipMemsetAsync(d_p, 0, sizeof(float) * np, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d_f, 0, sizeof(float) * nf, h->stream);
@@ -1037,7 +1045,7 @@ int lbm_set_proposal(lbm_t* h, const float* params, float threshold, int32_t ena
   if (!h->user.progressive) return fail(h, LBM_EINVAL, "the proposal needs a progressive mesh");
   if (!h->mlp_dev) {
     h->mlp_dev = (float*)dev_alloc(h, sizeof(float) * LBM_MLP_NPARAMS);
-    if (!h->mlp_dev) return fail(h, LBM_ENOMEM, "device allocation failed (proposal)");
+    if (!h->mlp_dev) return alloc_failed(h, "proposal");
   }
   HIP_TRY(h, hipMemcpy(h->mlp_dev, params, sizeof(float) * LBM_MLP_NPARAMS, hipMemcpyHostToDevice));
   h->prop_thr = threshold;
