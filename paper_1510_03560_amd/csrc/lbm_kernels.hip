@@ -995,8 +995,11 @@ __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int st
   const int step = BATCH ? D.ctrl[kStepCount] : step_arg;
   __shared__ int wave_count[16];
   __shared__ int wave_base[16];
+  __shared__ int order_count[2][16];  // active blocks per wave: before and after this pass's new slots
+  __shared__ int order_base[2][16];
+  __shared__ int order_total[2];
   __shared__ int chunk_total;
-  __shared__ int stop;
+  __shared__ int stop, chunk_stop;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int n0 = D.ctrl[kNActive];
   const int tr0 = D.ctrl[kTraceLen];
@@ -1007,76 +1010,77 @@ __global__ void __launch_bounds__(1024) k_activate(Params Pv, Buffers Dv, int st
     }
     return;
   }
-  int base = n0;
+  // one pass over the blocks, 1024 at a time: every array a block needs is
+  // loaded together, then two prefix sums (new slots, and the active list in
+  // block order, which is the order the step kernel schedules them in, so
+  // that neighbouring blocks run together and share one L2) take one round
+  // of barriers
+  int base = n0, obase = 0;
+  unsigned long long leak = 0ull;  // failing links recorded by the criterion into blocks still inactive
   if (t == 0) stop = 0;
-  __syncthreads();
   for (int b0 = 0; b0 < P.nb; b0 += 1024) {
     const int b = b0 + t;
-    int flag = 0;
-    if (b < P.nb && D.request[b]) flag = (D.block_slot[b] < 0 && D.bfluid[b]) ? 1 : 0;
+    int req = 0, sl = -1, fl = 0, e = 0;
+    if (b < P.nb) {
+      req = D.request[b];
+      sl = D.block_slot[b];
+      fl = D.bfluid[b];
+      e = D.expose[b];
+    }
+    const int flag = (req && sl < 0 && fl) ? 1 : 0;
     const unsigned long long bal = __ballot(flag);
-    const int lane_rank = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_count[wave] = __popcll(bal);
+    const unsigned long long bal_old = __ballot(sl >= 0);
+    const unsigned long long bal_new = bal | bal_old;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (lane == 0) {
+      wave_count[wave] = __popcll(bal);
+      order_count[0][wave] = __popcll(bal_old);
+      order_count[1][wave] = __popcll(bal_new);
+    }
+    // (the sums of the previous chunk are read by every thread before this
+    // barrier, and written again only after it)
     __syncthreads();
     if (t == 0) {
-      int acc = 0;
+      int acc = 0, acc_o[2] = {0, 0};
       for (int w = 0; w < 16; ++w) {
         wave_base[w] = acc;
         acc += wave_count[w];
+        for (int k = 0; k < 2; ++k) {
+          order_base[k][w] = acc_o[k];
+          acc_o[k] += order_count[k][w];
+        }
       }
       chunk_total = acc;
-      if (base + acc > P.capacity) stop = 1;
+      order_total[0] = acc_o[0];
+      order_total[1] = acc_o[1];
+      // pool full: no slot in this chunk or after; their requests stay
+      if (!stop && base + acc > P.capacity) stop = 1;
+      chunk_stop = stop;
     }
     __syncthreads();
-    if (stop) break;  // pool full: keep the remaining requests, report
-    if (flag) {
-      const int rank = base - n0 + wave_base[wave] + lane_rank;
-      const int slot = base + wave_base[wave] + lane_rank;
-      D.block_slot[b] = slot;
-      D.slot_block[slot] = b;
+    const bool assign = !chunk_stop;  // the same value for the whole workgroup
+    if (assign && flag) {
+      const int rank = base - n0 + wave_base[wave] + __popcll(bal & below);
+      sl = n0 + rank;
+      D.block_slot[b] = sl;
+      D.slot_block[sl] = b;
       D.act_step[b] = step;
       if (tr0 + rank < P.trace_cap) {
         D.trace[2 * (tr0 + rank)] = step;
         D.trace[2 * (tr0 + rank) + 1] = b;
       }
     }
-    if (b < P.nb) D.request[b] = 0;
-    base += chunk_total;
-    __syncthreads();
-  }
-  // the active slots in block order, which is the order the step kernel
-  // schedules them in (neighbouring blocks run together and share one L2)
-  int obase = 0;
-  for (int b0 = 0; b0 < P.nb; b0 += 1024) {
-    const int b = b0 + t;
-    const int sl = b < P.nb ? D.block_slot[b] : -1;
-    const int flag = sl >= 0 ? 1 : 0;
-    const unsigned long long bal = __ballot(flag);
-    const int lane_rank = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_count[wave] = __popcll(bal);
-    __syncthreads();
-    if (t == 0) {
-      int acc = 0;
-      for (int w = 0; w < 16; ++w) {
-        wave_base[w] = acc;
-        acc += wave_count[w];
-      }
-      chunk_total = acc;
-    }
-    __syncthreads();
-    if (flag) D.order[obase + wave_base[wave] + lane_rank] = sl;
-    obase += chunk_total;
-    __syncthreads();
-  }
-  // failing links recorded by the criterion: leaks if their block is still
-  // inactive now that this step's activations are done
-  unsigned long long leak = 0ull;
-  for (int b = t; b < P.nb; b += 1024) {
-    const int e = D.expose[b];
+    const int k = assign ? 1 : 0;
+    if (sl >= 0) D.order[obase + order_base[k][wave] + __popcll((assign ? bal_new : bal_old) & below)] = sl;
+    // a leak if the target block is still inactive now that this step's
+    // activations are done
     if (e) {
-      if (D.block_slot[b] < 0) leak += (unsigned long long)e;
+      if (sl < 0) leak += (unsigned long long)e;
       D.expose[b] = 0;
     }
+    if (assign && b < P.nb) D.request[b] = 0;
+    if (assign) base += chunk_total;
+    obase += order_total[k];
   }
   if (leak) atomicAdd(&D.counters[0], leak);
   if (t == 0) {
