@@ -1943,17 +1943,22 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
     }
     uint32_t bad = 0u;  // failing links
     if ((flags & kCritEmission) && out_links) {
-      uint32_t em[NC][kQ];
+      uint32_t em[NC][kQ] = {};
       unroll<kQ - 1>([&](auto I) {
         constexpr int i = decltype(I)::value + 1;
         constexpr int first = (i & 1) ? i : i - 1;
         // f*_i(x) is stored at (x, plane i), or with the in-place pattern
-        // at (x, opposite plane) after either parity of step
+        // at (x, opposite plane) after either parity of step.  Only the
+        // links into a candidate block are loaded (five of the eighteen for
+        // a cell on a face); the loads still go out together
         constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
-        typename S::T v[NC];
-        ld_link<typename S::T, NC>(fb + (size_t)first * plane * NC, (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(v), v);
+        if ((out_links >> i) & 1u) {
+          typename S::T v[NC];
+          ld_link<typename S::T, NC>(fb + (size_t)first * plane * NC, (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(v),
+                                     v);
 #pragma unroll
-        for (int a = 0; a < NC; ++a) em[a][i] = S::bits(v[a]);
+          for (int a = 0; a < NC; ++a) em[a][i] = S::bits(v[a]);
+        }
       });
       if constexpr (S::kRef) {
         float r[NC];
