@@ -162,6 +162,22 @@ def test_porous64_parity_vs_oracle(porous64):
     assert_parity(gp, r, label="porous64")
 
 
+def test_more_than_1024_blocks_progressive_equals_static(lbm):
+    """208 x 80 x 256 lattice, 13 x 5 x 16 = 1040 blocks: the activation pass
+    takes the blocks 1024 at a time, and the new slots and the block-order
+    list carry over from one group to the next.  The progressive mesh must
+    still reproduce the static one bit for bit (sections 4.1-4.3), and the
+    blocks it activates must come from both groups."""
+    case = W.porous_injection(shape=(208, 80, 256), steps=120)
+    gp, sp, tp = run_gpu(lbm, case, 120)
+    gs, ss, _ = run_gpu(lbm, case, 120, progressive=False)
+    assert sp["leak"] == 0 and sp["numeric_error"] == 0 and ss["numeric_error"] == 0
+    for a, b in zip(gp[:3], gs[:3]):
+        assert np.array_equal(a, b)
+    new = tp[int(case.active_blocks.sum()):, 1]
+    assert new.size > 0 and new.min() < 1024 <= new.max(), (new.min(), new.max())
+
+
 @pytest.mark.parametrize("ncomp,f16", [(2, False), (1, False), (2, True)])
 def test_seam_droplet_mesh_grows_across_periodic_faces(lbm, ncomp, f16):
     """A droplet on the periodic seam, progressive mesh from the eight corner
