@@ -1948,11 +1948,12 @@ __global__ void __launch_bounds__(kThreads) k_criterion(Params Pv, Buffers Dv, i
         constexpr int i = decltype(I)::value + 1;
         constexpr int first = (i & 1) ? i : i - 1;
         // f*_i(x) is stored at (x, plane i), or with the in-place pattern
-        // at (x, opposite plane) after either parity of step.  Only the
-        // links into a candidate block are loaded (five of the eighteen for
-        // a cell on a face); the loads still go out together
+        // at (x, opposite plane) after either parity of step.  FP32 store:
+        // only the links into a candidate block are loaded (five of the
+        // eighteen for a cell on a face; 8 % less time at 384^3).  FP16
+        // store: all eighteen (the same choice took 12 % more time there)
         constexpr bool upper = (RD == kRdAAEven || RD == kRdAAOdd) ? (i & 1) : !(i & 1);
-        if ((out_links >> i) & 1u) {
+        if (S::kRef || ((out_links >> i) & 1u)) {
           typename S::T v[NC];
           ld_link<typename S::T, NC>(fb + (size_t)first * plane * NC, (cid + (upper ? plane : 0u)) * (uint32_t)sizeof(v),
                                      v);
