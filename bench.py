@@ -447,6 +447,7 @@ def run_proposal(args):
                                  every=2, K=K)
         Xs.append(X)
         Ys.append(Y)
+        print(f"bench: training seed {seed}: {len(Y)} samples", file=sys.stderr, flush=True)
     X, Y = np.concatenate(Xs), np.concatenate(Ys)
     print(f"bench: proposal training set {len(Y)} samples ({int(Y.sum())} positive) in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
