@@ -1309,6 +1309,10 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
 #pragma unroll 1
   for (int k = 0; k < zlen + 2; ++k) {
     const int z = z0 + k - 1;
+    // FP32 store: the wave's pulls and psi run at raised priority, so that
+    // its loads go out ahead of the arithmetic of waves in their collision
+    // (0.659 -> 0.654 ms per 192^3 full-mesh launch)
+    if constexpr (!S::kRef) __builtin_amdgcn_s_setprio(1);
     const bool own = interior && z >= z0 && z < z0 + zlen;
     const uint32_t m = mask_s[k & 1][t];
     const uint32_t m_ahead = mask_load(z + 1);
@@ -1369,6 +1373,7 @@ __device__ __forceinline__ void fused_block(const Params& P, const Buffers& D, i
     mask_s[(k + 1) & 1][t] = in_mesh(z + 1) ? m_ahead : kNoCell;
     // (past the last plane the values land in a slot no later pull reads)
     if constexpr (S::kRef) rref_put(z + 2, rref_ahead);
+    if constexpr (!S::kRef) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // ---- plane z - 1: every cell of the block is stored, so that each
     // written cache line is complete (a partial line costs the memory a
